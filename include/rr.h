@@ -1,0 +1,206 @@
+/*
+ * rr.h -- ray reordering and closest-hit tracing on AMD Instinct MI355X (gfx950).
+ *
+ * Implements the data-parallel path of Meister, Boksansky, Guthe and Bittner,
+ * "On Ray Reordering Techniques for Faster GPU Ray Tracing" (I3D 2020):
+ * per-ray sort keys (Section 3.1, Figure "codes"), a key/index sort
+ * (Section 3.2), the ray-data reordering pass (Section 3.2, Section 4.4.1)
+ * and the closest-hit trace the reordering is meant to speed up (Section 4.1).
+ *
+ * Conventions for every function below:
+ *  - All functions are extern "C", never throw, and return rr_status.
+ *  - Array arguments are DEVICE pointers owned by the caller unless stated
+ *    otherwise; the library never frees them.  Sizes are element counts.
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL is
+ *    the default stream).  No function waits for the device unless stated.
+ *  - Argument errors are detected on the host before anything is enqueued
+ *    and return RR_ERR_INVALID_ARGUMENT (or RR_ERR_WORKSPACE_TOO_SMALL /
+ *    RR_ERR_UNSUPPORTED); launch failures return RR_ERR_DEVICE.  Faults
+ *    inside kernels surface at the caller's next synchronisation.
+ *  - n = 0 is valid and enqueues nothing (except that count outputs are
+ *    written as 0).
+ *  - Buffers given to one call must not overlap unless stated otherwise.
+ *  - The library allocates device memory only in rr_scene_create (owned by
+ *    the scene) and for its own small per-device state on first use.
+ */
+#ifndef RR_H
+#define RR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rr_status;
+#define RR_OK 0
+#define RR_ERR_INVALID_ARGUMENT (-1)
+#define RR_ERR_OUT_OF_MEMORY (-2)
+#define RR_ERR_DEVICE (-3)
+#define RR_ERR_UNSUPPORTED (-4)
+#define RR_ERR_WORKSPACE_TOO_SMALL (-5)
+#define RR_ERR_BUDGET (-6)
+
+/* Largest ray count a single call accepts (the sort's tile status words hold
+ * 30-bit counts). */
+#define RR_MAX_RAYS ((int64_t)1 << 30)
+
+/* A ray (Section 3: origin, direction and extent), 32 bytes, 16-byte
+ * aligned.  Valid hits satisfy tmin < t < tmax.  Directions are expected to
+ * be unit length (the keys quantise each component over [-1, 1]). */
+typedef struct rr_ray {
+  float org[3];
+  float tmin;
+  float dir[3];
+  float tmax;
+} rr_ray;
+
+/* Closest hit, 16 bytes.  prim is the index of the triangle in the array
+ * given to rr_scene_create; (u, v) are its barycentric coordinates along
+ * (v1 - v0, v2 - v0).  A miss is {+inf, -1, 0, 0}. */
+typedef struct rr_hit {
+  float t;
+  int32_t prim;
+  float u, v;
+} rr_hit;
+
+/* Sort-key methods of Section 3.1. */
+typedef enum rr_key_kind {
+  RR_KEY_NONE = 0,               /* no reordering (identity order) */
+  RR_KEY_ORIGIN_DIRECTION = 1,   /* Section 3.1.2 (Reis et al.): origin bits above direction bits */
+  RR_KEY_ORIGIN_TERMINATION = 2  /* Section 3.1.5 "Two Point": origin and estimated termination
+                                    point interleaved, fixed-length estimate of Section 3.1.6 */
+} rr_key_kind;
+
+/* Key parameters.
+ *  kind        one of rr_key_kind.
+ *  key_bits    32 or 64.
+ *  box_lo/hi   quantisation box for origins and termination points, normally
+ *              the scene bounds (rr_scene_bounds).  A flat axis quantises to 0.
+ *  term_ratio  Two Point only: estimated ray length = term_ratio x the
+ *              largest box extent, capped at the ray's tmax (Section 3.1.6
+ *              uses 0.25).
+ *  origin_bits origin-direction only: number of origin bits; 0 selects 22
+ *              for 32-bit keys (Figure "codes", Reis row) and 44 for 64-bit.
+ * Bit layout, most significant first: origin-direction = origin_bits slots
+ * cycling (o.x, o.y, o.z) then key_bits - origin_bits slots cycling
+ * (d.x, d.y, d.z); Two Point = key_bits slots cycling
+ * (o.x, o.y, o.z, t.x, t.y, t.z).  A component owning b slots is quantised
+ * as q = min(trunc(clamp((x - lo) / (hi - lo), 0, 1) * 2^b), 2^b - 1)
+ * (directions use lo = -1, hi = 1), its most significant bit in its first
+ * slot. */
+typedef struct rr_key_params {
+  int32_t kind;
+  uint32_t key_bits;
+  float box_lo[3];
+  float box_hi[3];
+  float term_ratio;
+  uint32_t origin_bits;
+} rr_key_params;
+
+typedef struct rr_scene_s* rr_scene;
+
+const char* rr_status_string(rr_status s);
+
+/* Number of visible HIP devices; fails with RR_ERR_DEVICE when none. */
+rr_status rr_device_count(int32_t* count);
+
+/* ------------------------------------------------------------------ scene
+ * Builds a binary BVH over n_tris triangles and uploads it to the current
+ * device.  tri_xyz_host is a HOST array of n_tris x 9 floats
+ * {v0.xyz, v1.xyz, v2.xyz}, read during the call only.  The scene owns its
+ * device memory until rr_scene_destroy; it is immutable and may be shared
+ * by concurrent calls on any stream of that device.
+ *  builder: 0 = median split (balanced, the default), 1 = binned surface
+ *  area heuristic.  Results of rr_trace do not depend on the builder. */
+rr_status rr_scene_create(const float* tri_xyz_host, int64_t n_tris, rr_scene* out);
+rr_status rr_scene_create_ex(const float* tri_xyz_host, int64_t n_tris, int32_t builder, rr_scene* out);
+rr_status rr_scene_bounds(rr_scene s, float lo[3], float hi[3]);
+/* Node count, tree depth and device bytes of the scene (any pointer may be NULL). */
+rr_status rr_scene_info(rr_scene s, int64_t* nodes, int32_t* depth, int64_t* device_bytes);
+rr_status rr_scene_destroy(rr_scene s);
+
+/* ------------------------------------------------------------------- keys
+ * Section 3.1: one key per ray.  keys_out holds uint32 (key_bits 32) or
+ * uint64 (key_bits 64) values; idx_out receives the ray index of each key.
+ * Without `alive` (NULL): keys_out[i] is the key of rays[i] and idx_out[i] = i;
+ * workspace may be NULL.
+ * With `alive` (n bytes, non-zero = live): only live rays are kept, in
+ * ascending index order (stable compaction of the terminated slots), and
+ * *count_out (device uint32, required) receives their number; entries past
+ * the count are left untouched.  The compaction needs a device workspace of
+ * rr_keys_workspace_size bytes (overwritten).  When alive is NULL, count_out
+ * may be NULL, else n is written to it.  kind must not be RR_KEY_NONE. */
+rr_status rr_keys_workspace_size(int64_t n, size_t* bytes);
+rr_status rr_compute_keys(const rr_ray* rays, int64_t n, const uint8_t* alive, const rr_key_params* p,
+                          void* keys_out, uint32_t* idx_out, uint32_t* count_out, void* workspace, size_t ws_bytes,
+                          void* stream);
+
+/* ------------------------------------------------------------------- sort
+ * Section 3.2: stable ascending LSD radix sort of (key, index) pairs, in
+ * place.  The result is unique: the lexicographic order of (key, index)
+ * when the input indices ascend.  n_max is the capacity; when count_dev
+ * (device uint32) is given, only its first *count_dev pairs are sorted
+ * (count_dev must not exceed n_max).  workspace (device, >= the size
+ * reported by rr_sort_workspace_size, 256-byte aligned) is scratch that the
+ * call overwrites. */
+rr_status rr_sort_workspace_size(int64_t n_max, uint32_t key_bits, size_t* bytes);
+rr_status rr_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                  void* workspace, size_t ws_bytes, void* stream);
+/* Same, with an explicit radix digit width (4 or 8 bits) and keys per
+ * thread (tile size); every choice gives the identical result. */
+rr_status rr_sort_ex(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                     uint32_t digit_bits, uint32_t keys_per_thread, void* workspace, size_t ws_bytes,
+                     void* stream);
+
+/* ----------------------------------------------------------------- gather
+ * Section 3.2, "an additional pass" that moves the ray data into key order:
+ * out[i] = in[idx[i]] for i < n (n = *count_dev when given, else n_max).
+ * in holds n_max rays and out n_max slots; they must not overlap.  An index
+ * >= n_max yields an all-NaN record instead of a read outside `in`. */
+rr_status rr_gather(const rr_ray* in, const uint32_t* idx, int64_t n_max, const uint32_t* count_dev, rr_ray* out,
+                    void* stream);
+
+/* Inverse of the gather for hits: out[idx[i]] = in[i] for i < n.  out holds
+ * n_max slots; slots not named by idx are left untouched and indices
+ * >= n_max are skipped. */
+rr_status rr_scatter_hits(const rr_hit* in, const uint32_t* idx, int64_t n_max, const uint32_t* count_dev,
+                          rr_hit* out, void* stream);
+
+/* ------------------------------------------------------------------ trace
+ * Closest hit of each ray (Section 4.1's nearest-hit kernel, here a
+ * software stack traversal of the scene BVH with a two-sided
+ * Moller-Trumbore triangle test in binary32).  The hit is the
+ * lexicographic minimum of (t, prim) over the triangles whose test passes
+ * with tmin < t < tmax, so it does not depend on ray order, BVH or launch
+ * shape.  hits[i] belongs to rays[i] for i < n (n = *count_dev when
+ * given). */
+rr_status rr_trace(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t* count_dev, rr_hit* hits,
+                   void* stream);
+
+/* --------------------------------------------------------- fused pipeline
+ * Keys (with compaction when `alive` is given), sort, gather and trace on
+ * one stream: the reordered trace of Section 3.2 / Section 4.4.1.
+ *  hits      device, n entries.  With RR_HITS_ORIGINAL_ORDER, hits[i] is the
+ *            hit of rays[i] and dead slots receive a miss record; otherwise
+ *            hits[i] belongs to the i-th ray in key order and entries past
+ *            the live count are untouched.
+ *  perm_out  optional device uint32[n]: the sorted ray indices (identity for
+ *            RR_KEY_NONE; compacted live indices when alive is given).
+ *  count_out optional device uint32: the number of traced rays.
+ *  workspace device scratch of at least rr_reorder_workspace_size bytes.
+ * RR_KEY_NONE traces the (compacted) rays in their original order. */
+#define RR_HITS_ORIGINAL_ORDER 1u
+/* Trace through the sorted index instead of gathering the rays first
+ * (Section 4.4.1, indirect ray access). */
+#define RR_INDIRECT 2u
+rr_status rr_reorder_workspace_size(int64_t n_max, const rr_key_params* p, size_t* bytes);
+rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const uint8_t* alive,
+                               const rr_key_params* p, rr_hit* hits, uint32_t* perm_out, uint32_t* count_out,
+                               uint32_t flags, void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RR_H */

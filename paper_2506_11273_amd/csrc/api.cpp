@@ -1,0 +1,324 @@
+// The C ABI of librr: argument validation, workspace layout and the
+// composition of the kernels into the reordered trace.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+
+namespace rr {
+rr_status build_scene(const float* tris, int64_t n, int builder, DeviceScene* out);
+}
+
+using namespace rr;
+
+namespace {
+
+bool valid_n(int64_t n) { return n >= 0 && n < RR_MAX_RAYS; }
+
+// Device pointers only: host memory passed where device memory is expected
+// would fault inside a kernel, so it is rejected up front.
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+struct ReorderLayout {
+  size_t keys, idx, count, kscratch, sortws, rays, hits, total;
+  size_t sort_bytes;
+};
+
+ReorderLayout reorder_layout(int64_t n, uint32_t key_bits) {
+  ReorderLayout L{};
+  size_t off = 0;
+  const size_t kb = key_bits / 8;
+  L.keys = off; off = align_up(off + kb * (size_t)n + 8, 256);
+  L.idx = off; off = align_up(off + 4 * (size_t)n + 4, 256);
+  L.count = off; off = align_up(off + 4, 256);
+  L.kscratch = off; off = align_up(off + keys_scratch_bytes(n), 256);
+  L.sort_bytes = sort_workspace_bytes_any(n, key_bits);
+  L.sortws = off; off = align_up(off + L.sort_bytes, 256);
+  L.rays = off; off = align_up(off + sizeof(rr_ray) * (size_t)n, 256);
+  L.hits = off; off = align_up(off + sizeof(rr_hit) * (size_t)n, 256);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rr_status_string(rr_status s) {
+  switch (s) {
+    case RR_OK: return "ok";
+    case RR_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case RR_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case RR_ERR_DEVICE: return "device (HIP) error";
+    case RR_ERR_UNSUPPORTED: return "unsupported";
+    case RR_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case RR_ERR_BUDGET: return "over budget";
+    default: return "unknown status";
+  }
+}
+
+rr_status rr_device_count(int32_t* count) {
+  if (!count) return RR_ERR_INVALID_ARGUMENT;
+  int c = 0;
+  if (hipGetDeviceCount(&c) != hipSuccess || c <= 0) {
+    (void)hipGetLastError();
+    *count = 0;
+    return RR_ERR_DEVICE;
+  }
+  *count = c;
+  return RR_OK;
+}
+
+// ------------------------------------------------------------------ scene
+
+rr_status rr_scene_create_ex(const float* tri, int64_t n_tris, int32_t builder, rr_scene* out) {
+  if (!out) return RR_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  if (!tri || n_tris <= 0 || n_tris >= (int64_t(1) << 28)) return RR_ERR_INVALID_ARGUMENT;
+  if (builder != 0 && builder != 1) return RR_ERR_INVALID_ARGUMENT;
+  for (int64_t i = 0; i < 9 * n_tris; ++i)
+    if (!std::isfinite(tri[i])) return RR_ERR_INVALID_ARGUMENT;
+  rr_scene s = new (std::nothrow) rr_scene_s;
+  if (!s) return RR_ERR_OUT_OF_MEMORY;
+  rr_status st;
+  try {
+    st = build_scene(tri, n_tris, builder, &s->d);
+  } catch (const std::bad_alloc&) {
+    st = RR_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    st = RR_ERR_DEVICE;
+  }
+  if (st != RR_OK) {
+    delete s;
+    return st;
+  }
+  *out = s;
+  return RR_OK;
+}
+
+rr_status rr_scene_create(const float* tri, int64_t n_tris, rr_scene* out) {
+  return rr_scene_create_ex(tri, n_tris, 0, out);
+}
+
+rr_status rr_scene_bounds(rr_scene s, float lo[3], float hi[3]) {
+  if (!s || !lo || !hi) return RR_ERR_INVALID_ARGUMENT;
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = s->d.lo[k];
+    hi[k] = s->d.hi[k];
+  }
+  return RR_OK;
+}
+
+rr_status rr_scene_info(rr_scene s, int64_t* nodes, int32_t* depth, int64_t* device_bytes) {
+  if (!s) return RR_ERR_INVALID_ARGUMENT;
+  if (nodes) *nodes = s->d.n_nodes;
+  if (depth) *depth = s->d.depth;
+  if (device_bytes) *device_bytes = (int64_t)s->d.bytes;
+  return RR_OK;
+}
+
+rr_status rr_scene_destroy(rr_scene s) {
+  if (!s) return RR_ERR_INVALID_ARGUMENT;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(s->d.device);
+  (void)hipFree(s->d.nodes);
+  (void)hipFree(s->d.tris);
+  (void)hipSetDevice(cur);
+  delete s;
+  return RR_OK;
+}
+
+// ------------------------------------------------------------------- keys
+
+rr_status rr_keys_workspace_size(int64_t n, size_t* bytes) {
+  if (!bytes || !valid_n(n)) return RR_ERR_INVALID_ARGUMENT;
+  *bytes = keys_scratch_bytes(n);
+  return RR_OK;
+}
+
+rr_status rr_compute_keys(const rr_ray* rays, int64_t n, const uint8_t* alive, const rr_key_params* p,
+                          void* keys_out, uint32_t* idx_out, uint32_t* count_out, void* workspace, size_t ws_bytes,
+                          void* stream) {
+  if (!valid_n(n) || !p) return RR_ERR_INVALID_ARGUMENT;
+  KeyPlan plan;
+  rr_status st = make_key_plan(p, &plan);
+  if (st != RR_OK) return st;
+  if (alive && !count_out) return RR_ERR_INVALID_ARGUMENT;
+  if (count_out && !is_device_ptr(count_out)) return RR_ERR_INVALID_ARGUMENT;
+  if (n == 0) return count_out ? launch_set_u32(count_out, 0u, S(stream)) : RR_OK;
+  if (!is_device_ptr(rays) || !aligned(rays, 16) || !is_device_ptr(keys_out) || !is_device_ptr(idx_out))
+    return RR_ERR_INVALID_ARGUMENT;
+  if (!aligned(keys_out, p->key_bits / 8) || !aligned(idx_out, 4)) return RR_ERR_INVALID_ARGUMENT;
+  if (alive) {
+    if (!is_device_ptr(alive)) return RR_ERR_INVALID_ARGUMENT;
+    if (!workspace || !is_device_ptr(workspace)) return RR_ERR_INVALID_ARGUMENT;
+    if (ws_bytes < keys_scratch_bytes(n)) return RR_ERR_WORKSPACE_TOO_SMALL;
+  }
+  return launch_keys(rays, n, alive, plan, keys_out, idx_out, count_out, workspace, S(stream));
+}
+
+// ------------------------------------------------------------------- sort
+
+rr_status rr_sort_workspace_size(int64_t n_max, uint32_t key_bits, size_t* bytes) {
+  if (!bytes || !valid_n(n_max) || (key_bits != 32 && key_bits != 64)) return RR_ERR_INVALID_ARGUMENT;
+  *bytes = sort_workspace_bytes_any(n_max, key_bits);
+  return RR_OK;
+}
+
+rr_status rr_sort_ex(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                     uint32_t digit_bits, uint32_t kpt, void* workspace, size_t ws_bytes, void* stream) {
+  if (!valid_n(n_max) || (key_bits != 32 && key_bits != 64)) return RR_ERR_INVALID_ARGUMENT;
+  if (!sort_config_supported(key_bits, digit_bits, kpt)) return RR_ERR_UNSUPPORTED;
+  if (n_max == 0) return RR_OK;
+  if (!is_device_ptr(keys) || !is_device_ptr(idx) || !is_device_ptr(workspace)) return RR_ERR_INVALID_ARGUMENT;
+  if (!aligned(keys, key_bits / 8) || !aligned(idx, 4) || !aligned(workspace, 256)) return RR_ERR_INVALID_ARGUMENT;
+  if (count_dev && !is_device_ptr(count_dev)) return RR_ERR_INVALID_ARGUMENT;
+  if (ws_bytes < sort_workspace_bytes(n_max, key_bits, digit_bits, kpt)) return RR_ERR_WORKSPACE_TOO_SMALL;
+  return launch_sort(keys, idx, n_max, count_dev, key_bits, digit_bits, kpt, workspace, ws_bytes, S(stream));
+}
+
+rr_status rr_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                  void* workspace, size_t ws_bytes, void* stream) {
+  return rr_sort_ex(keys, idx, n_max, count_dev, key_bits, 8, 16, workspace, ws_bytes, stream);
+}
+
+// ----------------------------------------------------------------- gather
+
+rr_status rr_gather(const rr_ray* in, const uint32_t* idx, int64_t n_max, const uint32_t* count_dev, rr_ray* out,
+                    void* stream) {
+  if (!valid_n(n_max)) return RR_ERR_INVALID_ARGUMENT;
+  if (n_max == 0) return RR_OK;
+  if (!is_device_ptr(in) || !is_device_ptr(idx) || !is_device_ptr(out)) return RR_ERR_INVALID_ARGUMENT;
+  if (!aligned(in, 16) || !aligned(out, 16) || !aligned(idx, 4)) return RR_ERR_INVALID_ARGUMENT;
+  if (count_dev && !is_device_ptr(count_dev)) return RR_ERR_INVALID_ARGUMENT;
+  const char* a = reinterpret_cast<const char*>(in);
+  const char* b = reinterpret_cast<const char*>(out);
+  const size_t bytes = sizeof(rr_ray) * (size_t)n_max;
+  if (a < b + bytes && b < a + bytes) return RR_ERR_INVALID_ARGUMENT;
+  return launch_gather(in, idx, n_max, count_dev, out, S(stream));
+}
+
+rr_status rr_scatter_hits(const rr_hit* in, const uint32_t* idx, int64_t n_max, const uint32_t* count_dev,
+                          rr_hit* out, void* stream) {
+  if (!valid_n(n_max)) return RR_ERR_INVALID_ARGUMENT;
+  if (n_max == 0) return RR_OK;
+  if (!is_device_ptr(in) || !is_device_ptr(idx) || !is_device_ptr(out)) return RR_ERR_INVALID_ARGUMENT;
+  if (!aligned(in, 16) || !aligned(out, 16) || !aligned(idx, 4)) return RR_ERR_INVALID_ARGUMENT;
+  if (count_dev && !is_device_ptr(count_dev)) return RR_ERR_INVALID_ARGUMENT;
+  const char* a = reinterpret_cast<const char*>(in);
+  const char* b = reinterpret_cast<const char*>(out);
+  const size_t bytes = sizeof(rr_hit) * (size_t)n_max;
+  if (a < b + bytes && b < a + bytes) return RR_ERR_INVALID_ARGUMENT;
+  return launch_scatter_hits(in, idx, n_max, count_dev, out, S(stream));
+}
+
+// ------------------------------------------------------------------ trace
+
+rr_status rr_trace(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t* count_dev, rr_hit* hits,
+                   void* stream) {
+  if (!s || !valid_n(n_max)) return RR_ERR_INVALID_ARGUMENT;
+  if (n_max == 0) return RR_OK;
+  if (!is_device_ptr(rays) || !is_device_ptr(hits) || !aligned(rays, 16) || !aligned(hits, 16))
+    return RR_ERR_INVALID_ARGUMENT;
+  if (count_dev && !is_device_ptr(count_dev)) return RR_ERR_INVALID_ARGUMENT;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != s->d.device) return RR_ERR_INVALID_ARGUMENT;
+  return launch_trace(s->d, rays, nullptr, n_max, count_dev, hits, S(stream));
+}
+
+// --------------------------------------------------------- fused pipeline
+
+rr_status rr_reorder_workspace_size(int64_t n_max, const rr_key_params* p, size_t* bytes) {
+  if (!bytes || !p || !valid_n(n_max)) return RR_ERR_INVALID_ARGUMENT;
+  const uint32_t kb = p->kind == RR_KEY_NONE ? 32u : p->key_bits;
+  if (kb != 32 && kb != 64) return RR_ERR_INVALID_ARGUMENT;
+  *bytes = reorder_layout(n_max, kb).total;
+  return RR_OK;
+}
+
+rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const uint8_t* alive,
+                               const rr_key_params* p, rr_hit* hits, uint32_t* perm_out, uint32_t* count_out,
+                               uint32_t flags, void* workspace, size_t ws_bytes, void* stream) {
+  if (!s || !p || !valid_n(n)) return RR_ERR_INVALID_ARGUMENT;
+  if (flags & ~(RR_HITS_ORIGINAL_ORDER | RR_INDIRECT)) return RR_ERR_INVALID_ARGUMENT;
+  const bool sorted = p->kind != RR_KEY_NONE;
+  KeyPlan plan{};
+  if (sorted) {
+    rr_status st = make_key_plan(p, &plan);
+    if (st != RR_OK) return st;
+  }
+  hipStream_t st = S(stream);
+  if (count_out && !is_device_ptr(count_out)) return RR_ERR_INVALID_ARGUMENT;
+  if (n == 0) return count_out ? launch_set_u32(count_out, 0u, st) : RR_OK;
+  if (!is_device_ptr(rays) || !is_device_ptr(hits) || !aligned(rays, 16) || !aligned(hits, 16))
+    return RR_ERR_INVALID_ARGUMENT;
+  if (alive && !is_device_ptr(alive)) return RR_ERR_INVALID_ARGUMENT;
+  if (perm_out && (!is_device_ptr(perm_out) || !aligned(perm_out, 4))) return RR_ERR_INVALID_ARGUMENT;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != s->d.device) return RR_ERR_INVALID_ARGUMENT;
+  const uint32_t kb = sorted ? p->key_bits : 32u;
+  const ReorderLayout L = reorder_layout(n, kb);
+  if (!workspace || !is_device_ptr(workspace) || !aligned(workspace, 256)) return RR_ERR_INVALID_ARGUMENT;
+  if (ws_bytes < L.total) return RR_ERR_WORKSPACE_TOO_SMALL;
+
+  char* w = reinterpret_cast<char*>(workspace);
+  void* keys = w + L.keys;
+  uint32_t* idx = reinterpret_cast<uint32_t*>(w + L.idx);
+  uint32_t* cnt = alive ? reinterpret_cast<uint32_t*>(w + L.count) : nullptr;
+  rr_ray* srays = reinterpret_cast<rr_ray*>(w + L.rays);
+  rr_hit* shits = reinterpret_cast<rr_hit*>(w + L.hits);
+  const bool orig = (flags & RR_HITS_ORIGINAL_ORDER) != 0;
+  const bool indirect = (flags & RR_INDIRECT) != 0;
+  rr_status r;
+
+  if (!sorted && !alive) {
+    // identity order: trace in place, both hit orders coincide
+    if ((r = launch_trace(s->d, rays, nullptr, n, nullptr, hits, st)) != RR_OK) return r;
+    if (perm_out && (r = launch_iota(perm_out, n, st)) != RR_OK) return r;
+    if (count_out && (r = launch_set_u32(count_out, (uint32_t)n, st)) != RR_OK) return r;
+    return RR_OK;
+  }
+
+  if (sorted) {
+    if ((r = launch_keys(rays, n, alive, plan, keys, idx, cnt, w + L.kscratch, st)) != RR_OK) return r;
+    if ((r = launch_sort(keys, idx, n, cnt, kb, 8, 16, w + L.sortws, L.sort_bytes, st)) != RR_OK) return r;
+  } else {
+    if ((r = launch_compact_only(n, alive, idx, cnt, w + L.kscratch, st)) != RR_OK) return r;
+  }
+  rr_hit* tout = orig ? shits : hits;
+  if (indirect) {
+    if ((r = launch_trace(s->d, rays, idx, n, cnt, tout, st)) != RR_OK) return r;
+  } else {
+    if ((r = launch_gather(rays, idx, n, cnt, srays, st)) != RR_OK) return r;
+    if ((r = launch_trace(s->d, srays, nullptr, n, cnt, tout, st)) != RR_OK) return r;
+  }
+  if (orig) {
+    if (alive && (r = launch_fill_miss(hits, n, st)) != RR_OK) return r;
+    if ((r = launch_scatter_hits(shits, idx, n, cnt, hits, st)) != RR_OK) return r;
+  }
+  if (perm_out && (r = launch_copy_u32(idx, perm_out, n, cnt, st)) != RR_OK) return r;
+  if (count_out) {
+    if (cnt) {
+      if ((r = launch_copy_u32(cnt, count_out, 1, nullptr, st)) != RR_OK) return r;
+    } else if ((r = launch_set_u32(count_out, (uint32_t)n, st)) != RR_OK) {
+      return r;
+    }
+  }
+  return RR_OK;
+}
+
+}  // extern "C"

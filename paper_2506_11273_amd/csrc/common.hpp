@@ -1,0 +1,91 @@
+// Internal declarations shared by the HIP translation units of librr.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "rr.h"
+
+namespace rr {
+
+// ------------------------------------------------------------- constants
+constexpr int kWave = 64;              // gfx950 wavefront width
+constexpr int kTraceStack = 32;        // per-lane traversal stack entries
+constexpr int kMaxTreeDepth = kTraceStack;  // a leaf at depth D needs at most D entries
+constexpr uint32_t kStatusCountMask = 0x3FFFFFFFu;
+constexpr uint32_t kStatusAggregate = 1u << 30;
+constexpr uint32_t kStatusPrefix = 2u << 30;
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// --------------------------------------------------------------- keys
+// Per-component quantisation plan computed on the host from rr_key_params:
+// component c (0-2 origin, 3-5 direction or termination point) owns
+// bits[c] key slots, spaced `stride` apart, its least significant bit
+// landing at key bit shift[c].
+struct KeyPlan {
+  float lo[3];
+  float inv[3];
+  float len;            // Two Point: fixed estimated length
+  float scale[6];       // 2^bits as float
+  uint32_t qmax[6];     // 2^bits - 1
+  int32_t shift[6];
+  int32_t kind;         // 1 origin-direction, 2 Two Point
+  int32_t key64;        // 0: 32-bit keys, 1: 64-bit keys
+};
+
+rr_status make_key_plan(const rr_key_params* p, KeyPlan* out);
+
+// Launchers (validated arguments; return RR_ERR_DEVICE on launch failure).
+rr_status launch_keys(const rr_ray* rays, int64_t n, const uint8_t* alive, const KeyPlan& plan, void* keys,
+                      uint32_t* idx, uint32_t* count_out, void* block_scratch, hipStream_t st);
+rr_status launch_compact_only(int64_t n, const uint8_t* alive, uint32_t* idx, uint32_t* count_out,
+                              void* block_scratch, hipStream_t st);
+size_t keys_scratch_bytes(int64_t n);
+
+// --------------------------------------------------------------- sort
+size_t sort_workspace_bytes(int64_t n_max, uint32_t key_bits, uint32_t digit_bits, uint32_t kpt);
+size_t sort_workspace_bytes_any(int64_t n_max, uint32_t key_bits);
+bool sort_config_supported(uint32_t key_bits, uint32_t digit_bits, uint32_t kpt);
+rr_status launch_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                      uint32_t digit_bits, uint32_t kpt, void* ws, size_t ws_bytes, hipStream_t st);
+
+// ------------------------------------------------------ gather / scatter
+rr_status launch_gather(const rr_ray* in, const uint32_t* idx, int64_t n_max, const uint32_t* count_dev, rr_ray* out,
+                        hipStream_t st);
+rr_status launch_scatter_hits(const rr_hit* in, const uint32_t* idx, int64_t n_max, const uint32_t* count_dev,
+                              rr_hit* out, hipStream_t st);
+rr_status launch_fill_miss(rr_hit* out, int64_t n, hipStream_t st);
+rr_status launch_copy_u32(const uint32_t* in, uint32_t* out, int64_t n_max, const uint32_t* count_dev, hipStream_t st);
+rr_status launch_iota(uint32_t* out, int64_t n, hipStream_t st);
+rr_status launch_set_u32(uint32_t* out, uint32_t value, hipStream_t st);
+
+// --------------------------------------------------------------- scene
+struct DeviceScene {
+  float4* nodes = nullptr;   // 4 float4 per inner node
+  float4* tris = nullptr;    // 3 float4 per triangle, leaf order
+  int32_t root = 0;          // inner node 0, or a leaf code
+  int64_t n_nodes = 0;
+  int64_t n_tris = 0;
+  int32_t depth = 0;
+  int32_t device = 0;
+  float lo[3], hi[3];
+  size_t bytes = 0;
+};
+
+rr_status launch_trace(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
+                       const uint32_t* count_dev, rr_hit* hits, hipStream_t st);
+
+}  // namespace rr
+
+struct rr_scene_s {
+  rr::DeviceScene d;
+};
+
+#define RR_LAUNCH_CHECK()                                   \
+  do {                                                      \
+    hipError_t e_ = hipGetLastError();                      \
+    if (e_ != hipSuccess) return RR_ERR_DEVICE;             \
+  } while (0)

@@ -1,0 +1,291 @@
+// Sort-key computation (Section 3.1, Figure "codes") with optional stable
+// compaction of live rays.
+//
+// Each key is the Morton-style interleave of quantised ray coordinates: an
+// origin-direction key (Section 3.1.2) puts the origin bits above the
+// direction bits, the Two Point key (Section 3.1.5) interleaves origin and
+// estimated termination point, the latter at a fixed length of a ratio of the
+// largest scene extent (Section 3.1.6).  Bits are placed with the classic
+// "spread by 3" magic-mask sequences rather than a per-slot loop: a component
+// with b slots at stride s has its bit i at key bit s*i + shift.
+//
+// The kernel is HBM bound: 32 bytes of ray in, 8 or 12 bytes out per ray.
+#include "common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace rr {
+
+rr_status make_key_plan(const rr_key_params* p, KeyPlan* out) {
+  if (!p || !out) return RR_ERR_INVALID_ARGUMENT;
+  if (p->key_bits != 32 && p->key_bits != 64) return RR_ERR_INVALID_ARGUMENT;
+  if (p->kind != RR_KEY_ORIGIN_DIRECTION && p->kind != RR_KEY_ORIGIN_TERMINATION) return RR_ERR_INVALID_ARGUMENT;
+  KeyPlan P{};
+  const int K = (int)p->key_bits;
+  float ext[3];
+  for (int k = 0; k < 3; ++k) {
+    ext[k] = p->box_hi[k] - p->box_lo[k];
+    P.lo[k] = p->box_lo[k];
+    P.inv[k] = ext[k] > 0.0f ? 1.0f / ext[k] : 0.0f;
+  }
+  float E = ext[0];
+  if (ext[1] > E) E = ext[1];
+  if (ext[2] > E) E = ext[2];
+  P.len = p->term_ratio * E;
+  P.kind = p->kind;
+  P.key64 = K == 64;
+
+  // A field of S slots starting at key bit `base`, cycling over `cyc`
+  // components: component j owns ceil((S - j) / cyc) slots; its slot m
+  // (from the field's top) sits at base + S - 1 - j - cyc*m and carries the
+  // component's bit b - 1 - m, hence bit i lands at cyc*i + shift.
+  auto place = [&](int first_comp, int ncomp, int cyc, int S, int base) {
+    for (int j = 0; j < ncomp; ++j) {
+      int c = first_comp + j;
+      int b = S > j ? (S - j + cyc - 1) / cyc : 0;
+      if (b <= 0) {
+        P.scale[c] = 1.0f;
+        P.qmax[c] = 0;
+        P.shift[c] = 0;
+        continue;
+      }
+      P.scale[c] = (float)(1u << b);
+      P.qmax[c] = (1u << b) - 1u;
+      P.shift[c] = base + S - 1 - j - cyc * (b - 1);
+    }
+  };
+  if (p->kind == RR_KEY_ORIGIN_DIRECTION) {
+    int ob = p->origin_bits ? (int)p->origin_bits : (K == 32 ? 22 : 44);
+    if (ob > K) return RR_ERR_INVALID_ARGUMENT;
+    place(0, 3, 3, ob, K - ob);
+    place(3, 3, 3, K - ob, 0);
+  } else {
+    // the six components cycle together over the whole key
+    int S = K;
+    for (int j = 0; j < 6; ++j) {
+      int b = (S - j + 5) / 6;
+      P.scale[j] = (float)(1u << b);
+      P.qmax[j] = (1u << b) - 1u;
+      P.shift[j] = S - 1 - j - 6 * (b - 1);
+    }
+  }
+  // spread3 interleaves components of at most 21 bits
+  for (int c = 0; c < 6; ++c)
+    if (P.qmax[c] >= (1u << 21)) return RR_ERR_UNSUPPORTED;
+  *out = P;
+  return RR_OK;
+}
+
+namespace {
+
+// bit i of x (i < 21) -> bit 3i
+__device__ __forceinline__ uint64_t spread3(uint64_t x) {
+  x &= 0x1FFFFFull;
+  x = (x | (x << 32)) & 0x001F00000000FFFFull;
+  x = (x | (x << 16)) & 0x001F0000FF0000FFull;
+  x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+  x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+// bit i of x (i < 16) -> bit 2i
+__device__ __forceinline__ uint64_t spread2(uint64_t x) {
+  x &= 0xFFFFull;
+  x = (x | (x << 8)) & 0x00FF00FFull;
+  x = (x | (x << 4)) & 0x0F0F0F0Full;
+  x = (x | (x << 2)) & 0x33333333ull;
+  x = (x | (x << 1)) & 0x55555555ull;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t quantize(float x, float lo, float inv, float scale, uint32_t qmax) {
+  float u = (x - lo) * inv;
+  u = (u > 0.0f) ? u : 0.0f;  // also maps NaN to 0
+  u = (u > 1.0f) ? 1.0f : u;
+  uint32_t q = (uint32_t)(u * scale);  // exact scaling, truncation
+  return q < qmax ? q : qmax;
+}
+
+template <int KIND>
+__device__ __forceinline__ uint64_t ray_key(const float4 a, const float4 b, const KeyPlan& P) {
+  // a = (org.xyz, tmin), b = (dir.xyz, tmax)
+  const uint32_t qx = quantize(a.x, P.lo[0], P.inv[0], P.scale[0], P.qmax[0]);
+  const uint32_t qy = quantize(a.y, P.lo[1], P.inv[1], P.scale[1], P.qmax[1]);
+  const uint32_t qz = quantize(a.z, P.lo[2], P.inv[2], P.scale[2], P.qmax[2]);
+  if constexpr (KIND == RR_KEY_ORIGIN_DIRECTION) {
+    const uint32_t dx = quantize(b.x, -1.0f, 0.5f, P.scale[3], P.qmax[3]);
+    const uint32_t dy = quantize(b.y, -1.0f, 0.5f, P.scale[4], P.qmax[4]);
+    const uint32_t dz = quantize(b.z, -1.0f, 0.5f, P.scale[5], P.qmax[5]);
+    return (spread3(qx) << P.shift[0]) | (spread3(qy) << P.shift[1]) | (spread3(qz) << P.shift[2]) |
+           (spread3(dx) << P.shift[3]) | (spread3(dy) << P.shift[4]) | (spread3(dz) << P.shift[5]);
+  } else {
+    const float len = (b.w < P.len) ? b.w : P.len;
+    const float sx = len * b.x, sy = len * b.y, sz = len * b.z;
+    const float tx = a.x + sx, ty = a.y + sy, tz = a.z + sz;
+    const uint32_t ux = quantize(tx, P.lo[0], P.inv[0], P.scale[3], P.qmax[3]);
+    const uint32_t uy = quantize(ty, P.lo[1], P.inv[1], P.scale[4], P.qmax[4]);
+    const uint32_t uz = quantize(tz, P.lo[2], P.inv[2], P.scale[5], P.qmax[5]);
+    // stride 6 = spread by 2, then by 3
+    return (spread3(spread2(qx)) << P.shift[0]) | (spread3(spread2(qy)) << P.shift[1]) |
+           (spread3(spread2(qz)) << P.shift[2]) | (spread3(spread2(ux)) << P.shift[3]) |
+           (spread3(spread2(uy)) << P.shift[4]) | (spread3(spread2(uz)) << P.shift[5]);
+  }
+}
+
+constexpr int kKeyBlock = 256;
+constexpr int kCompactPer = 4;
+constexpr int kCompactTile = kKeyBlock * kCompactPer;  // rays per compaction block
+
+template <int KIND, typename K>
+__global__ __launch_bounds__(kKeyBlock) void k_keys_dense(const float4* __restrict__ rays, uint32_t n, KeyPlan P,
+                                                          K* __restrict__ keys, uint32_t* __restrict__ idx,
+                                                          uint32_t* count_out) {
+  const uint32_t i = blockIdx.x * kKeyBlock + threadIdx.x;
+  if (i == 0 && count_out) *count_out = n;
+  if (i >= n) return;
+  const float4 a = rays[2 * (size_t)i];
+  const float4 b = rays[2 * (size_t)i + 1];
+  keys[i] = (K)ray_key<KIND>(a, b, P);
+  idx[i] = i;
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Live rays per block of kCompactTile slots.
+__global__ __launch_bounds__(kKeyBlock) void k_alive_count(const uint8_t* __restrict__ alive, uint32_t n,
+                                                           uint32_t* __restrict__ block_counts) {
+  __shared__ uint32_t s_sum;
+  if (threadIdx.x == 0) s_sum = 0;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * kCompactTile;
+  uint32_t c = 0;
+#pragma unroll
+  for (int r = 0; r < kCompactPer; ++r) {
+    const uint32_t i = base + r * kKeyBlock + threadIdx.x;
+    c += (i < n && alive[i]) ? 1u : 0u;
+  }
+  // wave sum by ballots over the 3 bits of c (c <= 4)
+  uint32_t w = 0;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) w += (uint32_t)__popcll(__ballot((c >> b) & 1u)) << b;
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&s_sum, w);
+  __syncthreads();
+  if (threadIdx.x == 0) block_counts[blockIdx.x] = s_sum;
+}
+
+// Exclusive scan of the block counts in place (one block of 1024 threads);
+// the total goes to *count_out.
+__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t* __restrict__ v, uint32_t nblocks,
+                                                      uint32_t* __restrict__ count_out) {
+  __shared__ uint32_t s[1024];
+  uint32_t running = 0;
+  for (uint32_t base = 0; base < nblocks; base += 1024) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t x = i < nblocks ? v[i] : 0u;
+    s[threadIdx.x] = x;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+      const uint32_t t = threadIdx.x >= off ? s[threadIdx.x - off] : 0u;
+      __syncthreads();
+      s[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nblocks) v[i] = running + s[threadIdx.x] - x;
+    running += s[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && count_out) *count_out = running;
+}
+
+// Keys (or only indices when WITH_KEYS is false) of the live rays, written
+// at their compacted positions: ascending original index.
+template <int KIND, typename K, bool WITH_KEYS>
+__global__ __launch_bounds__(kKeyBlock) void k_keys_compact(const float4* __restrict__ rays,
+                                                            const uint8_t* __restrict__ alive, uint32_t n, KeyPlan P,
+                                                            const uint32_t* __restrict__ block_off,
+                                                            K* __restrict__ keys, uint32_t* __restrict__ idx) {
+  __shared__ uint32_t s_w[kKeyBlock / kWave];
+  const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const uint32_t base = blockIdx.x * kCompactTile;
+  uint32_t running = block_off[blockIdx.x];
+  for (int r = 0; r < kCompactPer; ++r) {
+    const uint32_t i = base + r * kKeyBlock + threadIdx.x;
+    const bool live = i < n && alive[i];
+    const uint64_t m = __ballot(live);
+    if (lane == 0) s_w[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kKeyBlock / kWave; ++w) {
+      const uint32_t c = s_w[w];
+      before += w < wave ? c : 0u;
+      total += c;
+    }
+    if (live) {
+      const uint32_t pos = running + before + lanes_below(m);
+      if constexpr (WITH_KEYS) {
+        const float4 a = rays[2 * (size_t)i];
+        const float4 b = rays[2 * (size_t)i + 1];
+        keys[pos] = (K)ray_key<KIND>(a, b, P);
+      }
+      idx[pos] = i;
+    }
+    running += total;
+    __syncthreads();
+  }
+}
+
+template <int KIND, typename K>
+rr_status keys_impl(const rr_ray* rays, int64_t n, const uint8_t* alive, const KeyPlan& P, K* keys, uint32_t* idx,
+                    uint32_t* count_out, uint32_t* block_scratch, hipStream_t st) {
+  const float4* r4 = reinterpret_cast<const float4*>(rays);
+  if (!alive) {
+    const uint32_t blocks = (uint32_t)((n + kKeyBlock - 1) / kKeyBlock);
+    hipLaunchKernelGGL((k_keys_dense<KIND, K>), dim3(blocks), dim3(kKeyBlock), 0, st, r4, (uint32_t)n, P, keys, idx,
+                       count_out);
+    RR_LAUNCH_CHECK();
+    return RR_OK;
+  }
+  const uint32_t nb = (uint32_t)((n + kCompactTile - 1) / kCompactTile);
+  hipLaunchKernelGGL(k_alive_count, dim3(nb), dim3(kKeyBlock), 0, st, alive, (uint32_t)n, block_scratch);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_scratch, nb, count_out);
+  hipLaunchKernelGGL((k_keys_compact<KIND, K, true>), dim3(nb), dim3(kKeyBlock), 0, st, r4, alive, (uint32_t)n, P,
+                     block_scratch, keys, idx);
+  RR_LAUNCH_CHECK();
+  return RR_OK;
+}
+
+}  // namespace
+
+size_t keys_scratch_bytes(int64_t n) {
+  return align_up(sizeof(uint32_t) * (size_t)((n + kCompactTile - 1) / kCompactTile + 1), 256);
+}
+
+rr_status launch_keys(const rr_ray* rays, int64_t n, const uint8_t* alive, const KeyPlan& P, void* keys,
+                      uint32_t* idx, uint32_t* count_out, void* block_scratch, hipStream_t st) {
+  uint32_t* bs = reinterpret_cast<uint32_t*>(block_scratch);
+  if (P.kind == RR_KEY_ORIGIN_DIRECTION) {
+    if (P.key64) return keys_impl<1, uint64_t>(rays, n, alive, P, (uint64_t*)keys, idx, count_out, bs, st);
+    return keys_impl<1, uint32_t>(rays, n, alive, P, (uint32_t*)keys, idx, count_out, bs, st);
+  }
+  if (P.key64) return keys_impl<2, uint64_t>(rays, n, alive, P, (uint64_t*)keys, idx, count_out, bs, st);
+  return keys_impl<2, uint32_t>(rays, n, alive, P, (uint32_t*)keys, idx, count_out, bs, st);
+}
+
+rr_status launch_compact_only(int64_t n, const uint8_t* alive, uint32_t* idx, uint32_t* count_out,
+                              void* block_scratch, hipStream_t st) {
+  uint32_t* bs = reinterpret_cast<uint32_t*>(block_scratch);
+  const uint32_t nb = (uint32_t)((n + kCompactTile - 1) / kCompactTile);
+  KeyPlan P{};
+  hipLaunchKernelGGL(k_alive_count, dim3(nb), dim3(kKeyBlock), 0, st, alive, (uint32_t)n, bs);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs, nb, count_out);
+  hipLaunchKernelGGL((k_keys_compact<1, uint32_t, false>), dim3(nb), dim3(kKeyBlock), 0, st, nullptr, alive,
+                     (uint32_t)n, P, bs, nullptr, idx);
+  RR_LAUNCH_CHECK();
+  return RR_OK;
+}
+
+}  // namespace rr

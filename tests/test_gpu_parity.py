@@ -1,0 +1,310 @@
+"""GPU parity: every step of the HIP path against the CPU oracle.
+
+Keys and sort permutations must match bit for bit; hits must match exactly
+(the triangle test is evaluated in the same binary32 operation order on both
+sides), with the near-tie rule as the only allowed difference: a differing
+primitive is accepted only if the oracle's own test of the GPU's primitive
+passes with t within 1e-5 relative of the oracle's t.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rr():
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    import paper_2506_11273_amd as m
+    m.load()
+    return m
+
+
+DEV = "cuda"
+KINDS = [(O.KIND_OD, 32), (O.KIND_OD, 64), (O.KIND_OT, 32), (O.KIND_OT, 64)]
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def keys_np(t, bits):
+    a = t.cpu().numpy()
+    return a.view(np.uint32) if bits == 32 else a.view(np.uint64)
+
+
+def idx_np(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def assert_hits_match(gpu, ref, rays, tris, what=""):
+    """prim exact except near-ties; t, u, v bit-exact when prim matches."""
+    same = gpu["prim"] == ref["prim"]
+    bad = np.nonzero(~same)[0]
+    for i in bad[:1000]:
+        gp, op = int(gpu["prim"][i]), int(ref["prim"][i])
+        assert gp >= 0 and op >= 0, f"{what}: hit/miss mismatch at ray {i}: gpu {gp} oracle {op}"
+        ok, t, _, _ = O.mt(rays[i], tris[gp])
+        assert ok and abs(t - ref["t"][i]) <= 1e-5 * abs(ref["t"][i]), f"{what}: ray {i}"
+        assert abs(gpu["t"][i] - ref["t"][i]) <= 1e-5 * abs(ref["t"][i]), f"{what}: ray {i}"
+    assert len(bad) <= max(2, len(ref) // 10000), f"{what}: {len(bad)} near-tie differences"
+    m = same
+    assert np.array_equal(gpu["t"][m].view(np.uint32), ref["t"][m].view(np.uint32)), what
+    assert np.array_equal(gpu["u"][m].view(np.uint32), ref["u"][m].view(np.uint32)), what
+    assert np.array_equal(gpu["v"][m].view(np.uint32), ref["v"][m].view(np.uint32)), what
+
+
+# ------------------------------------------------------------------- keys
+
+@pytest.mark.parametrize("kind,bits", KINDS)
+def test_keys_bit_exact_soup(rr, soup65k, kind, bits):
+    w = soup65k
+    lo, hi = O.scene_box(w.tris)
+    p = rr.key_params(kind, bits, lo, hi, 0.25)
+    k, idx, _ = rr.rr_compute_keys(to_dev(w.rays), p)
+    torch.cuda.synchronize()
+    ref = O.keys(w.rays, kind, bits, lo, hi, 0.25)
+    assert np.array_equal(keys_np(k, bits), ref)
+    assert np.array_equal(idx_np(idx), np.arange(len(ref), dtype=np.uint32))
+
+
+@pytest.mark.parametrize("n", [1, 63, 255, 257, 1000])
+def test_keys_ragged_sizes_and_edge_values(rr, n):
+    rng = np.random.default_rng(n)
+    rays = np.zeros((n, 8), np.float32)
+    rays[:, 0:3] = rng.uniform(-0.5, 1.5, (n, 3))     # includes out-of-box origins
+    d = rng.normal(size=(n, 3))
+    rays[:, 4:7] = d / np.linalg.norm(d, axis=1, keepdims=True)
+    rays[:, 7] = np.where(rng.uniform(size=n) < 0.3, rng.uniform(0, 0.3, n), np.inf)
+    rays[0, 0:3] = [1.0, 1.0, 1.0]                     # on the upper face
+    rays[0, 4:7] = [0.0, 0.0, -1.0]
+    if n > 3:
+        rays[1, 0] = np.nan
+        rays[2, 4:7] = [1.0, 0.0, 0.0]
+    lo, hi = np.zeros(3, np.float32), np.ones(3, np.float32)
+    for kind, bits in KINDS:
+        for ratio in (0.25, 0.0):
+            p = rr.key_params(kind, bits, lo, hi, ratio)
+            k, _, _ = rr.rr_compute_keys(to_dev(rays), p)
+            ref = O.keys(rays, kind, bits, lo, hi, ratio)
+            assert np.array_equal(keys_np(k, bits), ref), (kind, bits, ratio)
+
+
+def test_keys_golden_values(rr):
+    import test_oracle_keys as T
+    for name, kind, bits, o, d, ratio, expected in T.load_golden():
+        r = np.array([[*o, 0, *d, np.inf]], np.float32)
+        p = rr.key_params(kind, bits, (0, 0, 0), (1, 1, 1), ratio)
+        k, _, _ = rr.rr_compute_keys(to_dev(r), p)
+        assert int(keys_np(k, bits)[0]) == expected, name
+
+
+def test_keys_compaction(rr):
+    w = W.city_small(seed=3, width=128, height=72, depth=2)
+    lo, hi = O.scene_box(w.tris)
+    live = O.compact(w.alive)
+    assert 0 < len(live) < len(w.alive)
+    for kind, bits in KINDS:
+        p = rr.key_params(kind, bits, lo, hi)
+        k, idx, cnt = rr.rr_compute_keys(to_dev(w.rays), p, alive=to_dev(w.alive))
+        c = int(cnt.cpu().numpy().view(np.uint32)[0])
+        assert c == len(live)
+        assert np.array_equal(idx_np(idx)[:c], live)
+        assert np.array_equal(keys_np(k, bits)[:c], O.keys(w.rays[live], kind, bits, lo, hi))
+
+
+def test_keys_compaction_all_dead_and_all_live(rr):
+    rays = W.random_rays(5, 3000)
+    p = rr.key_params(rr.RR_KEY_ORIGIN_DIRECTION, 32, (0, 0, 0), (1, 1, 1))
+    for alive in (np.zeros(3000, np.uint8), np.ones(3000, np.uint8)):
+        k, idx, cnt = rr.rr_compute_keys(to_dev(rays), p, alive=to_dev(alive))
+        c = int(cnt.cpu().numpy()[0])
+        assert c == int(alive.sum())
+        assert np.array_equal(idx_np(idx)[:c], O.compact(alive))
+
+
+# ------------------------------------------------------------------- sort
+
+def _random_keys(n, bits, seed, dup_bits):
+    rng = np.random.default_rng(seed)
+    if bits == 32:
+        k = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+        k &= np.uint32(~((1 << dup_bits) - 1) & 0xFFFFFFFF)
+    else:
+        k = rng.integers(0, 1 << 63, n, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, n, dtype=np.uint64)
+        k &= ~np.uint64((1 << dup_bits) - 1)
+    return k
+
+
+@pytest.mark.parametrize("n", [1, 2, 100, 4095, 4096, 4097, 65553, 300007])
+@pytest.mark.parametrize("bits", [32, 64])
+def test_sort_matches_stable_order(rr, n, bits):
+    for dup in (0, bits - 6):  # distinct-ish keys, then only 64 distinct values
+        k = _random_keys(n, bits, n + bits + dup, dup)
+        dt = torch.int32 if bits == 32 else torch.int64
+        kd = to_dev(k.view(np.int32 if bits == 32 else np.int64))
+        idx = torch.arange(n, dtype=torch.int32, device=DEV)
+        rr.rr_sort(kd, idx)
+        ks, ix = O.sort_pairs(k)
+        assert kd.dtype == dt
+        assert np.array_equal(keys_np(kd, bits), ks), (n, bits, dup)
+        assert np.array_equal(idx_np(idx), ix), (n, bits, dup)
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("digit_bits,kpt", [(8, 16), (8, 8), (4, 16), (4, 8)])
+def test_sort_every_configuration_identical(rr, bits, digit_bits, kpt):
+    n = 123457
+    k = _random_keys(n, bits, 99, bits - 10)
+    kd = to_dev(k.view(np.int32 if bits == 32 else np.int64))
+    idx = torch.arange(n, dtype=torch.int32, device=DEV)
+    rr.rr_sort(kd, idx, digit_bits=digit_bits, keys_per_thread=kpt)
+    ks, ix = O.sort_pairs(k)
+    assert np.array_equal(idx_np(idx), ix)
+    assert np.array_equal(keys_np(kd, bits), ks)
+
+
+def test_sort_device_count(rr):
+    n_max, n = 50000, 31337
+    k = _random_keys(n_max, 64, 5, 20)
+    kd = to_dev(k.view(np.int64))
+    idx = torch.arange(n_max, dtype=torch.int32, device=DEV)
+    cnt = torch.tensor([n], dtype=torch.int32, device=DEV)
+    rr.rr_sort(kd, idx, count=cnt)
+    ks, ix = O.sort_pairs(k[:n])
+    assert np.array_equal(idx_np(idx)[:n], ix)
+    assert np.array_equal(keys_np(kd, 64)[:n], ks)
+    # the tail beyond the count is untouched
+    assert np.array_equal(keys_np(kd, 64)[n:], k[n:])
+
+
+def test_sort_twice_is_deterministic(rr):
+    n = 200000
+    k = _random_keys(n, 32, 8, 12)
+    outs = []
+    for _ in range(2):
+        kd = to_dev(k.view(np.int32))
+        idx = torch.arange(n, dtype=torch.int32, device=DEV)
+        rr.rr_sort(kd, idx)
+        outs.append(idx_np(idx).copy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+# ----------------------------------------------------------------- gather
+
+def test_gather_and_scatter(rr):
+    rng = np.random.default_rng(3)
+    n = 100003
+    rays = rng.normal(size=(n, 8)).astype(np.float32)
+    perm = rng.permutation(n).astype(np.uint32)
+    g = rr.rr_gather(to_dev(rays), to_dev(perm.view(np.int32)))
+    assert np.array_equal(g.cpu().numpy(), rays[perm])
+    hits = rng.normal(size=(n, 4)).astype(np.float32)
+    s = rr.rr_scatter_hits(to_dev(hits), to_dev(perm.view(np.int32)))
+    assert np.array_equal(s.cpu().numpy()[perm], hits)
+
+
+# ------------------------------------------------------------------ trace
+
+@pytest.mark.parametrize("builder", [0, 1])
+def test_trace_soup_matches_brute_force(rr, soup65k, builder):
+    w = soup65k
+    ref = O.brute_force(w.tris, w.rays)
+    with rr.Scene(w.tris, builder=builder) as sc:
+        h = rr.hits_to_numpy(rr.rr_trace(sc, to_dev(w.rays)))
+    assert_hits_match(h, ref, w.rays, w.tris, f"soup builder {builder}")
+
+
+def test_trace_small_city_matches_oracle(rr):
+    w = W.city_small(seed=11, width=160, height=90, depth=1)
+    ref = O.BVH(w.tris).trace(w.rays)
+    for builder in (0, 1):
+        with rr.Scene(w.tris, builder=builder) as sc:
+            h = rr.hits_to_numpy(rr.rr_trace(sc, to_dev(w.rays)))
+        assert_hits_match(h, ref, w.rays, w.tris, f"city builder {builder}")
+
+
+def test_trace_tiny_scenes_and_ties(rr):
+    # one triangle (the root is a leaf); shared-edge tie goes to the lower id
+    a = [1, 0, 0.5, 0, 1, 0.5, 1, 1, 0.5]
+    b = [0, 0, 0.5, 1, 0, 0.5, 0, 1, 0.5]
+    rays = np.array([[0.5, 0.5, 0, 0, 0, 0, 1, np.inf],
+                     [0.25, 0.25, 0, 0, 0, 0, 1, np.inf],
+                     [0.25, 0.25, 0, 0, 0, 0, -1, np.inf],
+                     [0.25, 0.25, 0, 0, 0, 0, 1, 0.5]], np.float32)
+    for tris in ([b], [a, b], [b, a]):
+        T = np.array(tris, np.float32)
+        ref = O.brute_force(T, rays)
+        with rr.Scene(T) as sc:
+            h = rr.hits_to_numpy(rr.rr_trace(sc, to_dev(rays)))
+        assert h.tobytes() == ref.tobytes()
+
+
+# ---------------------------------------------------------- fused pipeline
+
+@pytest.mark.parametrize("kind,bits", KINDS + [(O.KIND_NONE, 32)])
+def test_reorder_and_trace_soup(rr, soup65k, kind, bits):
+    w = soup65k
+    bvh = O.BVH(w.tris)
+    lo, hi = O.scene_box(w.tris)
+    ref = O.reorder_and_trace(bvh, w.rays, kind, bits, lo, hi)
+    with rr.Scene(w.tris) as sc:
+        rays = to_dev(w.rays)
+        p = rr.key_params(kind, bits, lo, hi)
+        base = rr.hits_to_numpy(rr.rr_trace(sc, rays))
+        for flags in (0, rr.RR_INDIRECT, rr.RR_HITS_ORIGINAL_ORDER, rr.RR_HITS_ORIGINAL_ORDER | rr.RR_INDIRECT):
+            hits, perm, cnt = rr.rr_reorder_and_trace(sc, rays, p, flags=flags)
+            h = rr.hits_to_numpy(hits)
+            assert np.array_equal(idx_np(perm), ref["idx"]), flags
+            assert int(cnt.cpu().numpy()[0]) == len(w.rays)
+            if flags & rr.RR_HITS_ORIGINAL_ORDER:
+                assert h.tobytes() == base.tobytes(), flags      # scatter-back == unsorted, bit for bit
+            else:
+                assert_hits_match(h, ref["hits"], ref["rays"], w.tris, f"sorted {kind}/{bits}/{flags}")
+
+
+def test_reorder_and_trace_with_compaction(rr):
+    w = W.city_small(seed=5, width=128, height=72, depth=2)
+    bvh = O.BVH(w.tris)
+    lo, hi = O.scene_box(w.tris)
+    with rr.Scene(w.tris) as sc:
+        rays, alive = to_dev(w.rays), to_dev(w.alive)
+        full = rr.hits_to_numpy(rr.rr_trace(sc, rays))
+        for kind, bits in [(O.KIND_NONE, 32), (O.KIND_OD, 32), (O.KIND_OT, 64)]:
+            ref = O.reorder_and_trace(bvh, w.rays, kind, bits, lo, hi, alive=w.alive)
+            p = rr.key_params(kind, bits, lo, hi)
+            hits, perm, cnt = rr.rr_reorder_and_trace(sc, rays, p, alive=alive, flags=rr.RR_HITS_ORIGINAL_ORDER)
+            c = int(cnt.cpu().numpy()[0])
+            assert c == len(ref["idx"])
+            assert np.array_equal(idx_np(perm)[:c], ref["idx"])
+            h = rr.hits_to_numpy(hits)
+            live = w.alive.astype(bool)
+            assert h[live].tobytes() == full[live].tobytes()
+            assert np.all(h["prim"][~live] == -1) and np.all(np.isinf(h["t"][~live]))
+
+
+def test_zero_rays(rr, soup65k):
+    w = soup65k
+    with rr.Scene(w.tris[:10]) as sc:
+        rays = torch.empty((0, 8), dtype=torch.float32, device=DEV)
+        p = rr.key_params(rr.RR_KEY_ORIGIN_DIRECTION, 32, (0, 0, 0), (1, 1, 1))
+        hits, perm, cnt = rr.rr_reorder_and_trace(sc, rays, p, ws=rr.workspace(256, DEV))
+        assert int(cnt.cpu().numpy()[0]) == 0
+        assert rr.rr_trace(sc, rays).shape == (0, 4)
+
+
+def test_host_pointer_rejected(rr, soup65k):
+    with rr.Scene(soup65k.tris[:10]) as sc:
+        host = torch.zeros((10, 8), dtype=torch.float32)
+        with pytest.raises(ValueError):
+            rr.rr_trace(sc, host)
+        lib = rr.load()
+        hits = torch.empty((10, 4), dtype=torch.float32, device=DEV)
+        st = lib.rr_trace(sc.handle, host.data_ptr(), 10, None, hits.data_ptr(), None)
+        assert st == -1
