@@ -112,8 +112,9 @@ rr_status rr_device_count(int32_t* count);
  * {v0.xyz, v1.xyz, v2.xyz}, read during the call only.  The scene owns its
  * device memory until rr_scene_destroy; it is immutable and may be shared
  * by concurrent calls on any stream of that device.
- *  builder: 0 = median split (balanced, the default), 1 = binned surface
- *  area heuristic.  Results of rr_trace do not depend on the builder. */
+ *  builder (rr_scene_create_ex): 0 = median split (balanced), 1 = binned
+ *  surface area heuristic (what rr_scene_create uses).  Results of rr_trace
+ *  do not depend on the builder. */
 rr_status rr_scene_create(const float* tri_xyz_host, int64_t n_tris, rr_scene* out);
 rr_status rr_scene_create_ex(const float* tri_xyz_host, int64_t n_tris, int32_t builder, rr_scene* out);
 rr_status rr_scene_bounds(rr_scene s, float lo[3], float hi[3]);
@@ -178,6 +179,16 @@ rr_status rr_scatter_hits(const rr_hit* in, const uint32_t* idx, int64_t n_max, 
  * given). */
 rr_status rr_trace(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t* count_dev, rr_hit* hits,
                    void* stream);
+
+/* Profiling variant of rr_trace (Section 4.2 compares the control-flow
+ * efficiency of the trace kernel on sorted and unsorted rays): same hits,
+ * plus six device uint64 counters written to stats_dev (overwritten):
+ *   [0] loop trips summed over rays, [1] loop trips of each wavefront x 64
+ *       summed over wavefronts (so [0]/[1] is the SIMD efficiency),
+ *   [2] inner-node visits, [3] leaf visits, [4] triangle tests, [5] rays.
+ * Slower than rr_trace (global atomics); for measurement only. */
+rr_status rr_trace_profile(rr_scene s, const rr_ray* rays, int64_t n, rr_hit* hits, uint64_t* stats_dev,
+                           void* stream);
 
 /* --------------------------------------------------------- fused pipeline
  * Keys (with compaction when `alive` is given), sort, gather and trace on

@@ -12,5 +12,6 @@ from .rr import (  # noqa: F401
     RR_KEY_NONE, RR_KEY_ORIGIN_DIRECTION, RR_KEY_ORIGIN_TERMINATION,
     RR_HITS_ORIGINAL_ORDER, RR_INDIRECT,
     hits_to_numpy, key_params, keys_workspace_size, load, reorder_workspace_size, sort_workspace_size,
-    rr_compute_keys, rr_sort, rr_gather, rr_scatter_hits, rr_trace, rr_reorder_and_trace, workspace,
+    rr_compute_keys, rr_sort, rr_gather, rr_scatter_hits, rr_trace, rr_trace_profile, rr_reorder_and_trace,
+    workspace,
 )

@@ -110,7 +110,7 @@ rr_status rr_scene_create_ex(const float* tri, int64_t n_tris, int32_t builder, 
 }
 
 rr_status rr_scene_create(const float* tri, int64_t n_tris, rr_scene* out) {
-  return rr_scene_create_ex(tri, n_tris, 0, out);
+  return rr_scene_create_ex(tri, n_tris, 1, out);
 }
 
 rr_status rr_scene_bounds(rr_scene s, float lo[3], float hi[3]) {
@@ -238,6 +238,19 @@ rr_status rr_trace(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != s->d.device) return RR_ERR_INVALID_ARGUMENT;
   return launch_trace(s->d, rays, nullptr, n_max, count_dev, hits, S(stream));
+}
+
+rr_status rr_trace_profile(rr_scene s, const rr_ray* rays, int64_t n, rr_hit* hits, uint64_t* stats_dev,
+                           void* stream) {
+  if (!s || !valid_n(n)) return RR_ERR_INVALID_ARGUMENT;
+  if (!is_device_ptr(stats_dev) || !aligned(stats_dev, 8)) return RR_ERR_INVALID_ARGUMENT;
+  rr_status r = launch_fill_u32(reinterpret_cast<uint32_t*>(stats_dev), 12, 0u, S(stream));
+  if (r != RR_OK || n == 0) return r;
+  if (!is_device_ptr(rays) || !is_device_ptr(hits) || !aligned(rays, 16) || !aligned(hits, 16))
+    return RR_ERR_INVALID_ARGUMENT;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != s->d.device) return RR_ERR_INVALID_ARGUMENT;
+  return launch_trace_stats(s->d, rays, n, hits, stats_dev, S(stream));
 }
 
 // --------------------------------------------------------- fused pipeline

@@ -61,6 +61,7 @@ rr_status launch_fill_miss(rr_hit* out, int64_t n, hipStream_t st);
 rr_status launch_copy_u32(const uint32_t* in, uint32_t* out, int64_t n_max, const uint32_t* count_dev, hipStream_t st);
 rr_status launch_iota(uint32_t* out, int64_t n, hipStream_t st);
 rr_status launch_set_u32(uint32_t* out, uint32_t value, hipStream_t st);
+rr_status launch_fill_u32(uint32_t* out, uint32_t n, uint32_t value, hipStream_t st);  // small n only
 
 // --------------------------------------------------------------- scene
 struct DeviceScene {
@@ -75,6 +76,8 @@ struct DeviceScene {
   size_t bytes = 0;
 };
 
+rr_status launch_trace_stats(const DeviceScene& s, const rr_ray* rays, int64_t n_max, rr_hit* hits,
+                             uint64_t* stats_dev, hipStream_t st);
 rr_status launch_trace(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
                        const uint32_t* count_dev, rr_hit* hits, hipStream_t st);
 

@@ -62,8 +62,8 @@ __global__ __launch_bounds__(kBlock) void k_iota(uint32_t* __restrict__ out, uin
   if (i < n) out[i] = i;
 }
 
-__global__ void k_set_u32(uint32_t* out, uint32_t value) {
-  if (threadIdx.x == 0) *out = value;
+__global__ void k_set_u32(uint32_t* out, uint32_t n, uint32_t value) {
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) out[i] = value;
 }
 
 inline uint32_t blocks_for(uint64_t threads) { return (uint32_t)((threads + kBlock - 1) / kBlock); }
@@ -114,8 +114,10 @@ rr_status launch_iota(uint32_t* out, int64_t n, hipStream_t st) {
   return RR_OK;
 }
 
-rr_status launch_set_u32(uint32_t* out, uint32_t value, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, st, out, value);
+rr_status launch_set_u32(uint32_t* out, uint32_t value, hipStream_t st) { return launch_fill_u32(out, 1, value, st); }
+
+rr_status launch_fill_u32(uint32_t* out, uint32_t n, uint32_t value, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(256), 0, st, out, n, value);
   RR_LAUNCH_CHECK();
   return RR_OK;
 }

@@ -52,92 +52,123 @@ __device__ __forceinline__ bool slab(float lox, float hix, float loy, float hiy,
   return n <= f;
 }
 
+// Counters of the profiling variant (Section 4.2 profiles control-flow
+// efficiency): lane loop trips, wave loop trips x 64, inner-node visits,
+// leaf visits, triangle tests, rays.
+struct TraceStats {
+  unsigned long long lane_trips, wave_trips64, inner, leaves, tri_tests, rays;
+};
+
+__device__ void trace_stats_flush(TraceStats* st, uint32_t trips, uint32_t inner, uint32_t leaves, uint32_t tris,
+                                  uint32_t ray) {
+  // wave maximum of the trips (the wave runs until its longest lane ends)
+  uint32_t mx = trips;
+  for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, kWave));
+  atomicAdd(&st->lane_trips, (unsigned long long)trips);
+  atomicAdd(&st->inner, (unsigned long long)inner);
+  atomicAdd(&st->leaves, (unsigned long long)leaves);
+  atomicAdd(&st->tri_tests, (unsigned long long)tris);
+  atomicAdd(&st->rays, (unsigned long long)ray);
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&st->wave_trips64, 64ull * mx);
+}
+
+template <bool STATS>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(const float4* __restrict__ nodes,
                                                        const float4* __restrict__ tris, int32_t root,
                                                        const float4* __restrict__ rays,
                                                        const uint32_t* __restrict__ idx, const uint32_t* count_dev,
-                                                       uint32_t n_max, float4* __restrict__ hits) {
+                                                       uint32_t n_max, float4* __restrict__ hits,
+                                                       TraceStats* stats) {
   __shared__ int32_t s_stack[kTraceStack * kTraceBlock];
   const uint32_t n = read_count(count_dev, n_max);
   const uint32_t i = blockIdx.x * kTraceBlock + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t r = idx ? idx[i] : i;
-  if (r >= n_max) {
-    hits[i] = make_float4(__int_as_float(0x7f800000), __int_as_float(-1), 0.0f, 0.0f);
-    return;
-  }
-  const float4 ra = rays[2 * (size_t)r];
-  const float4 rb = rays[2 * (size_t)r + 1];
-  const float ox = ra.x, oy = ra.y, oz = ra.z, tmin = ra.w;
-  const float dx = rb.x, dy = rb.y, dz = rb.z;
-  const float ix = 1.0f / nudge(dx), iy = 1.0f / nudge(dy), iz = 1.0f / nudge(dz);
+  if (!STATS && i >= n) return;
+  // the profiling variant keeps every lane to the end for its wave reductions
+  const uint32_t r = i < n ? (idx ? idx[i] : i) : 0u;
+  const bool live = i < n && r < n_max;
+  if (i < n && !live) hits[i] = make_float4(__int_as_float(0x7f800000), __int_as_float(-1), 0.0f, 0.0f);
+  uint32_t trips = 0, n_inner = 0, n_leaf = 0, n_tri = 0;
+  if (live) {
+    const float4 ra = rays[2 * (size_t)r];
+    const float4 rb = rays[2 * (size_t)r + 1];
+    const float ox = ra.x, oy = ra.y, oz = ra.z, tmin = ra.w;
+    const float dx = rb.x, dy = rb.y, dz = rb.z;
+    const float ix = 1.0f / nudge(dx), iy = 1.0f / nudge(dy), iz = 1.0f / nudge(dz);
 
-  float tbest = rb.w;
-  int32_t bprim = -1;
-  float bu = 0.0f, bv = 0.0f;
+    float tbest = rb.w;
+    int32_t bprim = -1;
+    float bu = 0.0f, bv = 0.0f;
 
-  int32_t* stack = s_stack + threadIdx.x;
-  int sp = 0;
-  int32_t node = root;
-  while (true) {
-    if (node >= 0) {
-      const float4* N = nodes + 4 * (size_t)node;
-      const float4 n0 = N[0], n1 = N[1], n2 = N[2];
-      const int4 n3 = *reinterpret_cast<const int4*>(N + 3);
-      float t0, t1;
-      const bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, ox, oy, oz, ix, iy, iz, tmin, tbest, &t0);
-      const bool h1 = slab(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, ox, oy, oz, ix, iy, iz, tmin, tbest, &t1);
-      if (h0 && h1) {
-        const bool first0 = t0 <= t1;
-        // sp never exceeds the tree depth, which the builder caps at kTraceStack
-        if (sp < kTraceStack) {
-          stack[sp * kTraceBlock] = first0 ? n3.y : n3.x;
-          ++sp;
+    int32_t* stack = s_stack + threadIdx.x;
+    int sp = 0;
+    int32_t node = root;
+    while (true) {
+      if (STATS) ++trips;
+      if (node >= 0) {
+        if (STATS) ++n_inner;
+        const float4* N = nodes + 4 * (size_t)node;
+        const float4 n0 = N[0], n1 = N[1], n2 = N[2];
+        const int4 n3 = *reinterpret_cast<const int4*>(N + 3);
+        float t0, t1;
+        const bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, ox, oy, oz, ix, iy, iz, tmin, tbest, &t0);
+        const bool h1 = slab(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, ox, oy, oz, ix, iy, iz, tmin, tbest, &t1);
+        if (h0 && h1) {
+          const bool first0 = t0 <= t1;
+          // sp never exceeds the tree depth, which the builder caps at kTraceStack
+          if (sp < kTraceStack) {
+            stack[sp * kTraceBlock] = first0 ? n3.y : n3.x;
+            ++sp;
+          }
+          node = first0 ? n3.x : n3.y;
+          continue;
         }
-        node = first0 ? n3.x : n3.y;
-        continue;
-      }
-      if (h0 || h1) {
-        node = h0 ? n3.x : n3.y;
-        continue;
-      }
-    } else {
-      const int32_t code = ~node;
-      const int32_t first = code >> 3, count = code & 7;
-      for (int32_t k = 0; k < count; ++k) {
-        const float4* T = tris + 3 * (size_t)(first + k);
-        const float4 a = T[0], b = T[1], c = T[2];
-        const float e1x = a.w, e1y = b.x, e1z = b.y;
-        const float e2x = b.z, e2y = b.w, e2z = c.x;
-        const int32_t prim = __float_as_int(c.y);
-        const float sx = ox - a.x, sy = oy - a.y, sz = oz - a.z;
-        const float px = dy * e2z - dz * e2y;
-        const float py = dz * e2x - dx * e2z;
-        const float pz = dx * e2y - dy * e2x;
-        const float det = (e1x * px + e1y * py) + e1z * pz;
-        if (det == 0.0f) continue;
-        const float inv = 1.0f / det;
-        const float u = ((sx * px + sy * py) + sz * pz) * inv;
-        if (!(u >= 0.0f && u <= 1.0f)) continue;
-        const float qx = sy * e1z - sz * e1y;
-        const float qy = sz * e1x - sx * e1z;
-        const float qz = sx * e1y - sy * e1x;
-        const float v = ((dx * qx + dy * qy) + dz * qz) * inv;
-        if (!(v >= 0.0f && u + v <= 1.0f)) continue;
-        const float t = ((e2x * qx + e2y * qy) + e2z * qz) * inv;
-        if (t > tmin && (t < tbest || (t == tbest && prim < bprim))) {
-          tbest = t;
-          bprim = prim;
-          bu = u;
-          bv = v;
+        if (h0 || h1) {
+          node = h0 ? n3.x : n3.y;
+          continue;
+        }
+      } else {
+        const int32_t code = ~node;
+        const int32_t first = code >> 3, count = code & 7;
+        if (STATS) {
+          ++n_leaf;
+          n_tri += count;
+        }
+        for (int32_t k = 0; k < count; ++k) {
+          const float4* T = tris + 3 * (size_t)(first + k);
+          const float4 a = T[0], b = T[1], c = T[2];
+          const float e1x = a.w, e1y = b.x, e1z = b.y;
+          const float e2x = b.z, e2y = b.w, e2z = c.x;
+          const int32_t prim = __float_as_int(c.y);
+          const float sx = ox - a.x, sy = oy - a.y, sz = oz - a.z;
+          const float px = dy * e2z - dz * e2y;
+          const float py = dz * e2x - dx * e2z;
+          const float pz = dx * e2y - dy * e2x;
+          const float det = (e1x * px + e1y * py) + e1z * pz;
+          if (det == 0.0f) continue;
+          const float inv = 1.0f / det;
+          const float u = ((sx * px + sy * py) + sz * pz) * inv;
+          if (!(u >= 0.0f && u <= 1.0f)) continue;
+          const float qx = sy * e1z - sz * e1y;
+          const float qy = sz * e1x - sx * e1z;
+          const float qz = sx * e1y - sy * e1x;
+          const float v = ((dx * qx + dy * qy) + dz * qz) * inv;
+          if (!(v >= 0.0f && u + v <= 1.0f)) continue;
+          const float t = ((e2x * qx + e2y * qy) + e2z * qz) * inv;
+          if (t > tmin && (t < tbest || (t == tbest && prim < bprim))) {
+            tbest = t;
+            bprim = prim;
+            bu = u;
+            bv = v;
+          }
         }
       }
+      if (sp == 0) break;
+      --sp;
+      node = stack[sp * kTraceBlock];
     }
-    if (sp == 0) break;
-    --sp;
-    node = stack[sp * kTraceBlock];
+    hits[i] = make_float4(bprim >= 0 ? tbest : __int_as_float(0x7f800000), __int_as_float(bprim), bu, bv);
   }
-  hits[i] = make_float4(bprim >= 0 ? tbest : __int_as_float(0x7f800000), __int_as_float(bprim), bu, bv);
+  if (STATS) trace_stats_flush(stats, trips, n_inner, n_leaf, n_tri, live ? 1u : 0u);
 }
 
 }  // namespace
@@ -146,9 +177,20 @@ rr_status launch_trace(const DeviceScene& s, const rr_ray* rays, const uint32_t*
                        const uint32_t* count_dev, rr_hit* hits, hipStream_t st) {
   if (n_max <= 0) return RR_OK;
   const uint32_t blocks = (uint32_t)((n_max + kTraceBlock - 1) / kTraceBlock);
-  hipLaunchKernelGGL(k_trace, dim3(blocks), dim3(kTraceBlock), 0, st, s.nodes, s.tris, s.root,
+  hipLaunchKernelGGL(k_trace<false>, dim3(blocks), dim3(kTraceBlock), 0, st, s.nodes, s.tris, s.root,
                      reinterpret_cast<const float4*>(rays), idx, count_dev, (uint32_t)n_max,
-                     reinterpret_cast<float4*>(hits));
+                     reinterpret_cast<float4*>(hits), nullptr);
+  RR_LAUNCH_CHECK();
+  return RR_OK;
+}
+
+rr_status launch_trace_stats(const DeviceScene& s, const rr_ray* rays, int64_t n_max, rr_hit* hits,
+                             uint64_t* stats_dev, hipStream_t st) {
+  if (n_max <= 0) return RR_OK;
+  const uint32_t blocks = (uint32_t)((n_max + kTraceBlock - 1) / kTraceBlock);
+  hipLaunchKernelGGL(k_trace<true>, dim3(blocks), dim3(kTraceBlock), 0, st, s.nodes, s.tris, s.root,
+                     reinterpret_cast<const float4*>(rays), nullptr, nullptr, (uint32_t)n_max,
+                     reinterpret_cast<float4*>(hits), reinterpret_cast<TraceStats*>(stats_dev));
   RR_LAUNCH_CHECK();
   return RR_OK;
 }

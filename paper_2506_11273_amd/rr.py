@@ -45,7 +45,7 @@ EXPORTS = (
     "rr_scene_create", "rr_scene_create_ex", "rr_scene_bounds", "rr_scene_info", "rr_scene_destroy",
     "rr_keys_workspace_size", "rr_compute_keys",
     "rr_sort_workspace_size", "rr_sort", "rr_sort_ex",
-    "rr_gather", "rr_scatter_hits", "rr_trace",
+    "rr_gather", "rr_scatter_hits", "rr_trace", "rr_trace_profile",
     "rr_reorder_workspace_size", "rr_reorder_and_trace",
 )
 
@@ -94,6 +94,7 @@ def load():
         "rr_gather": ([vp, vp, i64, vp, vp, vp], st),
         "rr_scatter_hits": ([vp, vp, i64, vp, vp, vp], st),
         "rr_trace": ([vp, vp, i64, vp, vp, vp], st),
+        "rr_trace_profile": ([vp, vp, i64, vp, vp, vp], st),
         "rr_reorder_workspace_size": ([i64, P(KeyParams), P(sz)], st),
         "rr_reorder_and_trace": ([vp, vp, i64, vp, P(KeyParams), vp, vp, vp, u32, vp, sz, vp], st),
     }
@@ -180,7 +181,7 @@ class Scene:
     """A BVH over a host triangle array (M, 9) float32, resident on the
     current device until close()."""
 
-    def __init__(self, tris, builder: int = 0):
+    def __init__(self, tris, builder: int = 1):
         L = load()
         a = np.ascontiguousarray(tris, dtype=np.float32).reshape(-1, 9)
         h = ctypes.c_void_p()
@@ -315,6 +316,22 @@ def rr_trace(scene: Scene, rays, count=None, hits=None, stream=None):
                            _ptr(count, "count", torch.int32, False), _ptr(hits, "hits", torch.float32),
                            _stream(stream)), "rr_trace")
     return hits
+
+
+def rr_trace_profile(scene: Scene, rays, hits=None, stream=None) -> dict:
+    """Trace with the profiling counters; synchronises and returns them."""
+    torch = _torch()
+    n = _n_rows(rays)
+    hits = torch.empty((n, 4), dtype=torch.float32, device=rays.device) if hits is None else hits
+    st = torch.zeros(6, dtype=torch.int64, device=rays.device)
+    _check(load().rr_trace_profile(scene.handle, _ptr(rays, "rays", torch.float32), n,
+                                   _ptr(hits, "hits", torch.float32), _ptr(st, "stats", torch.int64),
+                                   _stream(stream)), "rr_trace_profile")
+    v = [int(x) for x in st.cpu().tolist()]
+    keys = ("lane_trips", "wave_trips64", "inner_visits", "leaf_visits", "tri_tests", "rays")
+    out = dict(zip(keys, v))
+    out["simd_efficiency"] = v[0] / v[1] if v[1] else 0.0
+    return out
 
 
 def rr_reorder_and_trace(scene: Scene, rays, params: KeyParams, alive=None, flags: int = RR_HITS_ORIGINAL_ORDER,
