@@ -180,6 +180,12 @@ rr_status rr_scatter_hits(const rr_hit* in, const uint32_t* idx, int64_t n_max, 
 rr_status rr_trace(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t* count_dev, rr_hit* hits,
                    void* stream);
 
+/* rr_trace with an explicit lane-refill threshold (1..64): a wavefront
+ * loads new rays into its idle lanes once at least `refill` lanes are idle
+ * (the traversal shape the autotuner varies).  Same hits for every value. */
+rr_status rr_trace_ex(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t* count_dev, rr_hit* hits,
+                      uint32_t refill, void* stream);
+
 /* Profiling variant of rr_trace (Section 4.2 compares the control-flow
  * efficiency of the trace kernel on sorted and unsorted rays): same hits,
  * plus six device uint64 counters written to stats_dev (overwritten):

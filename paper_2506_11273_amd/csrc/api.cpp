@@ -240,6 +240,18 @@ rr_status rr_trace(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t
   return launch_trace(s->d, rays, nullptr, n_max, count_dev, hits, S(stream));
 }
 
+rr_status rr_trace_ex(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t* count_dev, rr_hit* hits,
+                      uint32_t refill, void* stream) {
+  if (!s || !valid_n(n_max) || refill < 1 || refill > 64) return RR_ERR_INVALID_ARGUMENT;
+  if (n_max == 0) return RR_OK;
+  if (!is_device_ptr(rays) || !is_device_ptr(hits) || !aligned(rays, 16) || !aligned(hits, 16))
+    return RR_ERR_INVALID_ARGUMENT;
+  if (count_dev && !is_device_ptr(count_dev)) return RR_ERR_INVALID_ARGUMENT;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != s->d.device) return RR_ERR_INVALID_ARGUMENT;
+  return launch_trace_refill(s->d, rays, nullptr, n_max, count_dev, hits, refill, S(stream));
+}
+
 rr_status rr_trace_profile(rr_scene s, const rr_ray* rays, int64_t n, rr_hit* hits, uint64_t* stats_dev,
                            void* stream) {
   if (!s || !valid_n(n)) return RR_ERR_INVALID_ARGUMENT;

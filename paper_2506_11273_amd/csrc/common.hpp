@@ -12,8 +12,13 @@ namespace rr {
 
 // ------------------------------------------------------------- constants
 constexpr int kWave = 64;              // gfx950 wavefront width
-constexpr int kTraceStack = 32;        // per-lane traversal stack entries
-constexpr int kMaxTreeDepth = kTraceStack;  // a leaf at depth D needs at most D entries
+constexpr uint32_t kXcds = 8;          // MI355X: 8 accelerator dies (XCDs), 32 CUs each
+constexpr int kMaxTreeDepth = 32;      // binary BVH leaf depth cap (the builder enforces it)
+// A 4-wide traversal pushes at most 3 entries per level, and a 4-wide node is
+// never deeper than the binary node it was collapsed from.
+constexpr int kTraceStack4 = 3 * kMaxTreeDepth;
+constexpr int32_t kEmptyChild = 0x7FFFFFFF;  // unused child slot of a 4-wide node
+constexpr uint32_t kDefaultRefill = 16;      // idle lanes that trigger a wave refill
 constexpr uint32_t kStatusCountMask = 0x3FFFFFFFu;
 constexpr uint32_t kStatusAggregate = 1u << 30;
 constexpr uint32_t kStatusPrefix = 2u << 30;
@@ -65,7 +70,7 @@ rr_status launch_fill_u32(uint32_t* out, uint32_t n, uint32_t value, hipStream_t
 
 // --------------------------------------------------------------- scene
 struct DeviceScene {
-  float4* nodes = nullptr;   // 4 float4 per inner node
+  float4* nodes = nullptr;   // 8 float4 per 4-wide inner node
   float4* tris = nullptr;    // 3 float4 per triangle, leaf order
   int32_t root = 0;          // inner node 0, or a leaf code
   int64_t n_nodes = 0;
@@ -78,6 +83,8 @@ struct DeviceScene {
 
 rr_status launch_trace_stats(const DeviceScene& s, const rr_ray* rays, int64_t n_max, rr_hit* hits,
                              uint64_t* stats_dev, hipStream_t st);
+rr_status launch_trace_refill(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
+                              const uint32_t* count_dev, rr_hit* hits, uint32_t refill, hipStream_t st);
 rr_status launch_trace(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
                        const uint32_t* count_dev, rr_hit* hits, hipStream_t st);
 

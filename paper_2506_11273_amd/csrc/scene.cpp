@@ -9,8 +9,8 @@
 //    back to the median split when a subtree could otherwise exceed the
 //    trace kernel's stack depth.
 // Leaves hold at most 4 triangles.  Nodes are emitted in depth-first order
-// (a left child follows its parent), triangles in leaf order with their
-// edges e1 = v1 - v0, e2 = v2 - v0 precomputed in binary32.
+// (a first child follows its parent) as a 4-wide tree, triangles in leaf
+// order with their edges e1 = v1 - v0, e2 = v2 - v0 precomputed in binary32.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -170,6 +170,9 @@ struct Builder {
   }
 };
 
+// Emits the 4-wide BVH: each binary inner node is widened by repeatedly
+// replacing its largest-area inner child with that child's two children
+// until it has four children or only leaves remain.
 struct Packer {
   const float* tris;
   const std::vector<int32_t>& order;
@@ -196,20 +199,40 @@ struct Packer {
   int32_t pack(const BNode* n, int depth) {
     max_depth = std::max(max_depth, depth);
     if (!n->kid[0]) return leaf(n);
-    const int32_t me = (int32_t)(nodes.size() / 4);
-    nodes.resize(nodes.size() + 4);
-    const int32_t c0 = pack(n->kid[0].get(), depth + 1);
-    const int32_t c1 = pack(n->kid[1].get(), depth + 1);
-    const Box& a = n->kid[0]->box;
-    const Box& b = n->kid[1]->box;
-    float4* N = nodes.data() + 4 * (size_t)me;
-    N[0] = make_float4(a.lo[0], a.hi[0], a.lo[1], a.hi[1]);
-    N[1] = make_float4(b.lo[0], b.hi[0], b.lo[1], b.hi[1]);
-    N[2] = make_float4(a.lo[2], a.hi[2], b.lo[2], b.hi[2]);
-    float f0, f1;
-    std::memcpy(&f0, &c0, 4);
-    std::memcpy(&f1, &c1, 4);
-    N[3] = make_float4(f0, f1, 0.0f, 0.0f);
+    const BNode* kids[4] = {n->kid[0].get(), n->kid[1].get(), nullptr, nullptr};
+    int m = 2;
+    while (m < 4) {
+      int best = -1;
+      double best_area = -1.0;
+      for (int j = 0; j < m; ++j)
+        if (kids[j]->kid[0] && kids[j]->box.area() > best_area) {
+          best = j;
+          best_area = kids[j]->box.area();
+        }
+      if (best < 0) break;
+      const BNode* x = kids[best];
+      kids[best] = x->kid[0].get();
+      kids[m++] = x->kid[1].get();
+    }
+    const int32_t me = (int32_t)(nodes.size() / 8);
+    nodes.resize(nodes.size() + 8);
+    int32_t code[4] = {kEmptyChild, kEmptyChild, kEmptyChild, kEmptyChild};
+    for (int j = 0; j < m; ++j) code[j] = pack(kids[j], depth + 1);
+    float lo[3][4], hi[3][4];
+    for (int j = 0; j < 4; ++j)
+      for (int k = 0; k < 3; ++k) {
+        lo[k][j] = j < m ? kids[j]->box.lo[k] : 0.0f;
+        hi[k][j] = j < m ? kids[j]->box.hi[k] : 0.0f;
+      }
+    float4* N = nodes.data() + 8 * (size_t)me;
+    for (int k = 0; k < 3; ++k) {
+      N[2 * k] = make_float4(lo[k][0], lo[k][1], lo[k][2], lo[k][3]);
+      N[2 * k + 1] = make_float4(hi[k][0], hi[k][1], hi[k][2], hi[k][3]);
+    }
+    float c[4];
+    std::memcpy(c, code, sizeof c);
+    N[6] = make_float4(c[0], c[1], c[2], c[3]);
+    N[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     return me;
   }
 };
@@ -231,14 +254,14 @@ rr_status build_scene(const float* tris, int64_t n, int builder, DeviceScene* ou
   Builder B(prims, order, builder);
   std::unique_ptr<BNode> root = B.build(0, n, 0);
   Packer P{tris, order, {}, {}, 0};
-  P.nodes.reserve((size_t)(n / 2 + 4) * 4);
+  P.nodes.reserve((size_t)(n / 4 + 8) * 8);
   P.gtris.reserve((size_t)n * 3);
   const int32_t root_code = P.pack(root.get(), 0);
   if (P.max_depth > kMaxTreeDepth) return RR_ERR_UNSUPPORTED;
 
   DeviceScene d;
   d.root = root_code;
-  d.n_nodes = (int64_t)(P.nodes.size() / 4);
+  d.n_nodes = (int64_t)(P.nodes.size() / 8);
   d.n_tris = n;
   d.depth = P.max_depth;
   for (int k = 0; k < 3; ++k) {
@@ -246,7 +269,7 @@ rr_status build_scene(const float* tris, int64_t n, int builder, DeviceScene* ou
     d.hi[k] = scene.hi[k];
   }
   if (hipGetDevice(&d.device) != hipSuccess) return RR_ERR_DEVICE;
-  const size_t nb = std::max<size_t>(P.nodes.size(), 4) * sizeof(float4);
+  const size_t nb = std::max<size_t>(P.nodes.size(), 8) * sizeof(float4);
   const size_t tb = P.gtris.size() * sizeof(float4);
   if (hipMalloc(&d.nodes, nb) != hipSuccess) return RR_ERR_OUT_OF_MEMORY;
   if (hipMalloc(&d.tris, tb) != hipSuccess) {

@@ -1,5 +1,5 @@
-// Closest-hit trace: software stack traversal of the scene's binary BVH with
-// a two-sided Moller-Trumbore triangle test in binary32 (the nearest-hit
+// Closest-hit trace: software stack traversal of a 4-wide BVH with a
+// two-sided Moller-Trumbore triangle test in binary32 (the nearest-hit
 // kernel of Section 4.1; the paper's method is agnostic to the trace kernel,
 // Section 1).
 //
@@ -9,16 +9,24 @@
 // (ray, triangle) pair always yields the same bits; the box test is
 // conservative (zero direction components are nudged to a tiny value and the
 // far distance gets a small relative slack), so pruning never removes the
-// defining minimum and the result does not depend on ray order or launch
-// shape.
+// defining minimum and the result does not depend on ray order, BVH or
+// launch shape.
 //
-// Layout: an inner node is 4 x float4 = 64 bytes holding both children's
-// boxes, (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y), (c1.lo.x, c1.hi.x, c1.lo.y,
-// c1.hi.y), (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z), (child0, child1, -, -).
-// A child >= 0 is an inner node; a child < 0 is a leaf ~(first << 3 | count).
+// Layout: an inner node is 8 x float4 = 128 bytes, its four child boxes in
+// SoA form: lo.x[4], hi.x[4], lo.y[4], hi.y[4], lo.z[4], hi.z[4], child[4],
+// unused.  A child >= 0 is an inner node, kEmptyChild an unused slot, and a
+// child < 0 a leaf ~(first << 3 | count) of at most 4 triangles.
 // A triangle is 3 x float4 = 48 bytes: (v0, e1.x), (e1.yz, e2.xy),
 // (e2.z, prim id bits, -, -), with e1 = v1 - v0 and e2 = v2 - v0.
-// The per-lane stack lives in LDS, interleaved by lane.
+//
+// Execution: persistent wavefronts.  Wave w owns a contiguous chunk of the
+// rays (in key order when the rays were reordered) and refills its idle
+// lanes from that chunk whenever at least `refill` lanes are idle, so lanes
+// whose rays finish early do not idle until the wave's longest ray ends.
+// The traversal stack holds at most 3 entries per tree level; its first
+// kLdsStack entries live in LDS (interleaved by lane), the rest in scratch.
+#include <algorithm>
+
 #include "common.hpp"
 
 #pragma clang fp contract(off)
@@ -26,9 +34,10 @@
 namespace rr {
 namespace {
 
-constexpr int kTraceBlock = 256;
 constexpr float kFarSlack = 0x1p-16f;
 constexpr float kTinyDir = 1e-20f;
+constexpr int kLdsStack = 16;
+constexpr int kSpillStack = kTraceStack4 - kLdsStack;
 
 __device__ __forceinline__ uint32_t read_count(const uint32_t* count_dev, uint32_t n_max) {
   if (!count_dev) return n_max;
@@ -38,161 +47,258 @@ __device__ __forceinline__ uint32_t read_count(const uint32_t* count_dev, uint32
 
 __device__ __forceinline__ float nudge(float d) { return fabsf(d) < kTinyDir ? copysignf(kTinyDir, d) : d; }
 
-// Slab test of one child box; returns the entry distance in *tn.
-__device__ __forceinline__ bool slab(float lox, float hix, float loy, float hiy, float loz, float hiz, float ox,
-                                     float oy, float oz, float ix, float iy, float iz, float tmin, float tbest,
-                                     float* tn) {
-  const float ax = (lox - ox) * ix, bx = (hix - ox) * ix;
-  const float ay = (loy - oy) * iy, by = (hiy - oy) * iy;
-  const float az = (loz - oz) * iz, bz = (hiz - oz) * iz;
-  const float n = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), tmin));
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Counters of the profiling variant (Section 4.2 profiles control-flow
+// efficiency): active lane iterations, wave iterations x 64, inner-node
+// visits, leaf visits, triangle tests, rays.
+struct TraceStats {
+  unsigned long long lane_trips, wave_trips64, inner, leaves, tri_tests, rays;
+};
+
+struct Ray {
+  float ox, oy, oz, tmin;
+  float dx, dy, dz, tmax;
+  float ix, iy, iz;
+};
+
+// Slab test of one child box; *tn receives the entry distance.
+__device__ __forceinline__ bool slab(float lx, float hx, float ly, float hy, float lz, float hz, const Ray& R,
+                                     float tbest, float* tn) {
+  const float ax = (lx - R.ox) * R.ix, bx = (hx - R.ox) * R.ix;
+  const float ay = (ly - R.oy) * R.iy, by = (hy - R.oy) * R.iy;
+  const float az = (lz - R.oz) * R.iz, bz = (hz - R.oz) * R.iz;
+  const float n = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), R.tmin));
   float f = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tbest));
   f = __builtin_fmaf(fabsf(f), kFarSlack, f);
   *tn = n;
   return n <= f;
 }
 
-// Counters of the profiling variant (Section 4.2 profiles control-flow
-// efficiency): lane loop trips, wave loop trips x 64, inner-node visits,
-// leaf visits, triangle tests, rays.
-struct TraceStats {
-  unsigned long long lane_trips, wave_trips64, inner, leaves, tri_tests, rays;
-};
+__device__ __forceinline__ void cswap(float& ta, int32_t& ca, float& tb, int32_t& cb) {
+  const bool s = tb < ta;
+  const float t = s ? tb : ta;
+  tb = s ? ta : tb;
+  ta = t;
+  const int32_t c = s ? cb : ca;
+  cb = s ? ca : cb;
+  ca = c;
+}
 
-__device__ void trace_stats_flush(TraceStats* st, uint32_t trips, uint32_t inner, uint32_t leaves, uint32_t tris,
-                                  uint32_t ray) {
-  // wave maximum of the trips (the wave runs until its longest lane ends)
-  uint32_t mx = trips;
-  for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, kWave));
-  atomicAdd(&st->lane_trips, (unsigned long long)trips);
-  atomicAdd(&st->inner, (unsigned long long)inner);
-  atomicAdd(&st->leaves, (unsigned long long)leaves);
-  atomicAdd(&st->tri_tests, (unsigned long long)tris);
-  atomicAdd(&st->rays, (unsigned long long)ray);
-  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&st->wave_trips64, 64ull * mx);
+template <int BLOCK, bool STATS>
+__global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nodes, const float4* __restrict__ tris,
+                                                  int32_t root, const float4* __restrict__ rays,
+                                                  const uint32_t* __restrict__ idx, const uint32_t* count_dev,
+                                                  uint32_t n_max, float4* __restrict__ hits, uint32_t refill,
+                                                  TraceStats* stats) {
+  __shared__ int32_t s_stack[kLdsStack * BLOCK];
+  int32_t spill[kSpillStack];
+  const uint32_t n = read_count(count_dev, n_max);
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t waves = gridDim.x * (BLOCK / kWave);
+  // Workgroups are dispatched to the XCDs round-robin; renumber them so that
+  // each XCD works on one contiguous share of the rays, which keeps the part
+  // of the BVH its L2 must hold small when the rays are spatially sorted.
+  const uint32_t nb = gridDim.x, q = nb / kXcds, rem = nb % kXcds;
+  const uint32_t x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+  const uint32_t lb = (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + j;
+  const uint32_t w = lb * (BLOCK / kWave) + threadIdx.x / kWave;
+  // this wave's contiguous chunk of ray slots
+  uint32_t next = (uint32_t)(((uint64_t)w * n) / waves);
+  const uint32_t end = (uint32_t)(((uint64_t)(w + 1) * n) / waves);
+  int32_t* lstack = s_stack + threadIdx.x;
+
+  Ray R{};
+  int32_t slot = -1;  // ray slot this lane works on, -1 when idle
+  int32_t node = 0;
+  int sp = 0;
+  float tbest = 0.0f, bu = 0.0f, bv = 0.0f;
+  int32_t bprim = -1;
+  unsigned long long st_trips = 0, st_wave = 0, st_inner = 0, st_leaf = 0, st_tri = 0, st_rays = 0;
+
+  while (true) {
+    // ---- refill idle lanes from the chunk (wave-uniform decision)
+    const uint64_t idle = __ballot(slot < 0);
+    const uint32_t n_idle = (uint32_t)__popcll(idle);
+    if (n_idle == kWave && next >= end) break;
+    if (next < end && (n_idle >= refill || n_idle == kWave)) {
+      if (slot < 0) {
+        const uint32_t s = next + lanes_below(idle);
+        if (s < end) {
+          slot = (int32_t)s;
+          const uint32_t r = idx ? idx[s] : s;
+          if (r < n_max) {
+            const float4 a = rays[2 * (size_t)r];
+            const float4 b = rays[2 * (size_t)r + 1];
+            R.ox = a.x; R.oy = a.y; R.oz = a.z; R.tmin = a.w;
+            R.dx = b.x; R.dy = b.y; R.dz = b.z; R.tmax = b.w;
+            R.ix = 1.0f / nudge(b.x);
+            R.iy = 1.0f / nudge(b.y);
+            R.iz = 1.0f / nudge(b.z);
+            tbest = b.w;
+            node = root;
+          } else {
+            // an index outside the rays: report a miss without tracing
+            tbest = __int_as_float(0x7f800000);
+            node = kEmptyChild;
+          }
+          bprim = -1;
+          bu = bv = 0.0f;
+          sp = 0;
+          if (STATS) ++st_rays;
+        }
+      }
+      next = next + n_idle < end ? next + n_idle : end;
+    }
+    if (STATS) st_wave += kWave;
+    if (slot < 0) continue;
+    if (STATS) ++st_trips;
+
+    // ---- one traversal step
+    bool pop = true;
+    if (node >= 0 && node != kEmptyChild) {
+      if (STATS) ++st_inner;
+      const float4* N = nodes + 8 * (size_t)node;
+      const float4 lx = N[0], hx = N[1], ly = N[2], hy = N[3], lz = N[4], hz = N[5];
+      const int4 cc = *reinterpret_cast<const int4*>(N + 6);
+      float t0, t1, t2, t3;
+      const bool h0 = slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, R, tbest, &t0) && cc.x != kEmptyChild;
+      const bool h1 = slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, R, tbest, &t1) && cc.y != kEmptyChild;
+      const bool h2 = slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, R, tbest, &t2) && cc.z != kEmptyChild;
+      const bool h3 = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, R, tbest, &t3) && cc.w != kEmptyChild;
+      const int m = (int)h0 + (int)h1 + (int)h2 + (int)h3;
+      if (m > 0) {
+        const float inf = __int_as_float(0x7f800000);
+        float d0 = h0 ? t0 : inf, d1 = h1 ? t1 : inf, d2 = h2 ? t2 : inf, d3 = h3 ? t3 : inf;
+        int32_t c0 = cc.x, c1 = cc.y, c2 = cc.z, c3 = cc.w;
+        // nearest first; misses (inf) sort last
+        cswap(d0, c0, d1, c1);
+        cswap(d2, c2, d3, c3);
+        cswap(d0, c0, d2, c2);
+        cswap(d1, c1, d3, c3);
+        cswap(d1, c1, d2, c2);
+        // push the farther hits, farthest first, so the next nearest pops first
+        const int32_t cs[3] = {c1, c2, c3};
+#pragma unroll
+        for (int k = 2; k >= 0; --k) {
+          if (k + 1 < m) {
+            if (sp < kLdsStack) lstack[sp * BLOCK] = cs[k];
+            else spill[sp - kLdsStack] = cs[k];
+            ++sp;
+          }
+        }
+        node = c0;
+        pop = false;
+      }
+    } else if (node < 0) {
+      const int32_t code = ~node;
+      const int32_t first = code >> 3, count = code & 7;
+      if (STATS) {
+        ++st_leaf;
+        st_tri += (unsigned long long)count;
+      }
+      for (int32_t k = 0; k < count; ++k) {
+        const float4* T = tris + 3 * (size_t)(first + k);
+        const float4 a = T[0], b = T[1], c = T[2];
+        const float e1x = a.w, e1y = b.x, e1z = b.y;
+        const float e2x = b.z, e2y = b.w, e2z = c.x;
+        const int32_t prim = __float_as_int(c.y);
+        const float sx = R.ox - a.x, sy = R.oy - a.y, sz = R.oz - a.z;
+        const float px = R.dy * e2z - R.dz * e2y;
+        const float py = R.dz * e2x - R.dx * e2z;
+        const float pz = R.dx * e2y - R.dy * e2x;
+        const float det = (e1x * px + e1y * py) + e1z * pz;
+        if (det == 0.0f) continue;
+        const float inv = 1.0f / det;
+        const float u = ((sx * px + sy * py) + sz * pz) * inv;
+        if (!(u >= 0.0f && u <= 1.0f)) continue;
+        const float qx = sy * e1z - sz * e1y;
+        const float qy = sz * e1x - sx * e1z;
+        const float qz = sx * e1y - sy * e1x;
+        const float v = ((R.dx * qx + R.dy * qy) + R.dz * qz) * inv;
+        if (!(v >= 0.0f && u + v <= 1.0f)) continue;
+        const float t = ((e2x * qx + e2y * qy) + e2z * qz) * inv;
+        if (t > R.tmin && (t < tbest || (t == tbest && prim < bprim))) {
+          tbest = t;
+          bprim = prim;
+          bu = u;
+          bv = v;
+        }
+      }
+    }
+    if (pop) {
+      if (sp == 0) {
+        hits[slot] = make_float4(bprim >= 0 ? tbest : __int_as_float(0x7f800000), __int_as_float(bprim), bu, bv);
+        slot = -1;
+      } else {
+        --sp;
+        node = sp < kLdsStack ? lstack[sp * BLOCK] : spill[sp - kLdsStack];
+      }
+    }
+  }
+  if (STATS) {
+    atomicAdd(&stats->lane_trips, st_trips);
+    atomicAdd(&stats->inner, st_inner);
+    atomicAdd(&stats->leaves, st_leaf);
+    atomicAdd(&stats->tri_tests, st_tri);
+    atomicAdd(&stats->rays, st_rays);
+    if (lane == 0) atomicAdd(&stats->wave_trips64, st_wave);
+  }
+}
+
+constexpr int kTraceBlock = 256;
+
+template <bool STATS>
+uint32_t resident_blocks() {
+  static uint32_t cached[2] = {0, 0};
+  if (cached[STATS]) return cached[STATS];
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace4<kTraceBlock, STATS>, kTraceBlock, 0) !=
+          hipSuccess ||
+      per <= 0)
+    per = 4;
+  cached[STATS] = (uint32_t)(cus * per);
+  return cached[STATS];
 }
 
 template <bool STATS>
-__global__ __launch_bounds__(kTraceBlock) void k_trace(const float4* __restrict__ nodes,
-                                                       const float4* __restrict__ tris, int32_t root,
-                                                       const float4* __restrict__ rays,
-                                                       const uint32_t* __restrict__ idx, const uint32_t* count_dev,
-                                                       uint32_t n_max, float4* __restrict__ hits,
-                                                       TraceStats* stats) {
-  __shared__ int32_t s_stack[kTraceStack * kTraceBlock];
-  const uint32_t n = read_count(count_dev, n_max);
-  const uint32_t i = blockIdx.x * kTraceBlock + threadIdx.x;
-  if (!STATS && i >= n) return;
-  // the profiling variant keeps every lane to the end for its wave reductions
-  const uint32_t r = i < n ? (idx ? idx[i] : i) : 0u;
-  const bool live = i < n && r < n_max;
-  if (i < n && !live) hits[i] = make_float4(__int_as_float(0x7f800000), __int_as_float(-1), 0.0f, 0.0f);
-  uint32_t trips = 0, n_inner = 0, n_leaf = 0, n_tri = 0;
-  if (live) {
-    const float4 ra = rays[2 * (size_t)r];
-    const float4 rb = rays[2 * (size_t)r + 1];
-    const float ox = ra.x, oy = ra.y, oz = ra.z, tmin = ra.w;
-    const float dx = rb.x, dy = rb.y, dz = rb.z;
-    const float ix = 1.0f / nudge(dx), iy = 1.0f / nudge(dy), iz = 1.0f / nudge(dz);
-
-    float tbest = rb.w;
-    int32_t bprim = -1;
-    float bu = 0.0f, bv = 0.0f;
-
-    int32_t* stack = s_stack + threadIdx.x;
-    int sp = 0;
-    int32_t node = root;
-    while (true) {
-      if (STATS) ++trips;
-      if (node >= 0) {
-        if (STATS) ++n_inner;
-        const float4* N = nodes + 4 * (size_t)node;
-        const float4 n0 = N[0], n1 = N[1], n2 = N[2];
-        const int4 n3 = *reinterpret_cast<const int4*>(N + 3);
-        float t0, t1;
-        const bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, ox, oy, oz, ix, iy, iz, tmin, tbest, &t0);
-        const bool h1 = slab(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, ox, oy, oz, ix, iy, iz, tmin, tbest, &t1);
-        if (h0 && h1) {
-          const bool first0 = t0 <= t1;
-          // sp never exceeds the tree depth, which the builder caps at kTraceStack
-          if (sp < kTraceStack) {
-            stack[sp * kTraceBlock] = first0 ? n3.y : n3.x;
-            ++sp;
-          }
-          node = first0 ? n3.x : n3.y;
-          continue;
-        }
-        if (h0 || h1) {
-          node = h0 ? n3.x : n3.y;
-          continue;
-        }
-      } else {
-        const int32_t code = ~node;
-        const int32_t first = code >> 3, count = code & 7;
-        if (STATS) {
-          ++n_leaf;
-          n_tri += count;
-        }
-        for (int32_t k = 0; k < count; ++k) {
-          const float4* T = tris + 3 * (size_t)(first + k);
-          const float4 a = T[0], b = T[1], c = T[2];
-          const float e1x = a.w, e1y = b.x, e1z = b.y;
-          const float e2x = b.z, e2y = b.w, e2z = c.x;
-          const int32_t prim = __float_as_int(c.y);
-          const float sx = ox - a.x, sy = oy - a.y, sz = oz - a.z;
-          const float px = dy * e2z - dz * e2y;
-          const float py = dz * e2x - dx * e2z;
-          const float pz = dx * e2y - dy * e2x;
-          const float det = (e1x * px + e1y * py) + e1z * pz;
-          if (det == 0.0f) continue;
-          const float inv = 1.0f / det;
-          const float u = ((sx * px + sy * py) + sz * pz) * inv;
-          if (!(u >= 0.0f && u <= 1.0f)) continue;
-          const float qx = sy * e1z - sz * e1y;
-          const float qy = sz * e1x - sx * e1z;
-          const float qz = sx * e1y - sy * e1x;
-          const float v = ((dx * qx + dy * qy) + dz * qz) * inv;
-          if (!(v >= 0.0f && u + v <= 1.0f)) continue;
-          const float t = ((e2x * qx + e2y * qy) + e2z * qz) * inv;
-          if (t > tmin && (t < tbest || (t == tbest && prim < bprim))) {
-            tbest = t;
-            bprim = prim;
-            bu = u;
-            bv = v;
-          }
-        }
-      }
-      if (sp == 0) break;
-      --sp;
-      node = stack[sp * kTraceBlock];
-    }
-    hits[i] = make_float4(bprim >= 0 ? tbest : __int_as_float(0x7f800000), __int_as_float(bprim), bu, bv);
-  }
-  if (STATS) trace_stats_flush(stats, trips, n_inner, n_leaf, n_tri, live ? 1u : 0u);
+rr_status launch4(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
+                  const uint32_t* count_dev, rr_hit* hits, uint32_t refill, TraceStats* stats, hipStream_t st) {
+  if (n_max <= 0) return RR_OK;
+  // enough waves to fill the device, but at least one full wave of rays each
+  const uint64_t waves_needed = (uint64_t)(n_max + kWave - 1) / kWave;
+  const uint64_t blocks_needed = (waves_needed + kTraceBlock / kWave - 1) / (kTraceBlock / kWave);
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>(blocks_needed, resident_blocks<STATS>());
+  if (refill < 1) refill = 1;
+  if (refill > (uint32_t)kWave) refill = kWave;
+  hipLaunchKernelGGL((k_trace4<kTraceBlock, STATS>), dim3(blocks), dim3(kTraceBlock), 0, st, s.nodes, s.tris,
+                     s.root, reinterpret_cast<const float4*>(rays), idx, count_dev, (uint32_t)n_max,
+                     reinterpret_cast<float4*>(hits), refill, stats);
+  RR_LAUNCH_CHECK();
+  return RR_OK;
 }
 
 }  // namespace
 
 rr_status launch_trace(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
                        const uint32_t* count_dev, rr_hit* hits, hipStream_t st) {
-  if (n_max <= 0) return RR_OK;
-  const uint32_t blocks = (uint32_t)((n_max + kTraceBlock - 1) / kTraceBlock);
-  hipLaunchKernelGGL(k_trace<false>, dim3(blocks), dim3(kTraceBlock), 0, st, s.nodes, s.tris, s.root,
-                     reinterpret_cast<const float4*>(rays), idx, count_dev, (uint32_t)n_max,
-                     reinterpret_cast<float4*>(hits), nullptr);
-  RR_LAUNCH_CHECK();
-  return RR_OK;
+  return launch4<false>(s, rays, idx, n_max, count_dev, hits, kDefaultRefill, nullptr, st);
+}
+
+rr_status launch_trace_refill(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
+                              const uint32_t* count_dev, rr_hit* hits, uint32_t refill, hipStream_t st) {
+  return launch4<false>(s, rays, idx, n_max, count_dev, hits, refill, nullptr, st);
 }
 
 rr_status launch_trace_stats(const DeviceScene& s, const rr_ray* rays, int64_t n_max, rr_hit* hits,
                              uint64_t* stats_dev, hipStream_t st) {
-  if (n_max <= 0) return RR_OK;
-  const uint32_t blocks = (uint32_t)((n_max + kTraceBlock - 1) / kTraceBlock);
-  hipLaunchKernelGGL(k_trace<true>, dim3(blocks), dim3(kTraceBlock), 0, st, s.nodes, s.tris, s.root,
-                     reinterpret_cast<const float4*>(rays), nullptr, nullptr, (uint32_t)n_max,
-                     reinterpret_cast<float4*>(hits), reinterpret_cast<TraceStats*>(stats_dev));
-  RR_LAUNCH_CHECK();
-  return RR_OK;
+  return launch4<true>(s, rays, nullptr, n_max, nullptr, hits, kDefaultRefill,
+                       reinterpret_cast<TraceStats*>(stats_dev), st);
 }
 
 }  // namespace rr

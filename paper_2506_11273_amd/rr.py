@@ -45,7 +45,7 @@ EXPORTS = (
     "rr_scene_create", "rr_scene_create_ex", "rr_scene_bounds", "rr_scene_info", "rr_scene_destroy",
     "rr_keys_workspace_size", "rr_compute_keys",
     "rr_sort_workspace_size", "rr_sort", "rr_sort_ex",
-    "rr_gather", "rr_scatter_hits", "rr_trace", "rr_trace_profile",
+    "rr_gather", "rr_scatter_hits", "rr_trace", "rr_trace_ex", "rr_trace_profile",
     "rr_reorder_workspace_size", "rr_reorder_and_trace",
 )
 
@@ -95,6 +95,7 @@ def load():
         "rr_scatter_hits": ([vp, vp, i64, vp, vp, vp], st),
         "rr_trace": ([vp, vp, i64, vp, vp, vp], st),
         "rr_trace_profile": ([vp, vp, i64, vp, vp, vp], st),
+        "rr_trace_ex": ([vp, vp, i64, vp, vp, u32, vp], st),
         "rr_reorder_workspace_size": ([i64, P(KeyParams), P(sz)], st),
         "rr_reorder_and_trace": ([vp, vp, i64, vp, P(KeyParams), vp, vp, vp, u32, vp, sz, vp], st),
     }
@@ -308,13 +309,18 @@ def rr_scatter_hits(hits, idx, count=None, out=None, stream=None):
     return out
 
 
-def rr_trace(scene: Scene, rays, count=None, hits=None, stream=None):
+def rr_trace(scene: Scene, rays, count=None, hits=None, refill: Optional[int] = None, stream=None):
     torch = _torch()
     n = _n_rows(rays)
     hits = torch.empty((n, 4), dtype=torch.float32, device=rays.device) if hits is None else hits
-    _check(load().rr_trace(scene.handle, _ptr(rays, "rays", torch.float32), n,
-                           _ptr(count, "count", torch.int32, False), _ptr(hits, "hits", torch.float32),
-                           _stream(stream)), "rr_trace")
+    if refill is None:
+        _check(load().rr_trace(scene.handle, _ptr(rays, "rays", torch.float32), n,
+                               _ptr(count, "count", torch.int32, False), _ptr(hits, "hits", torch.float32),
+                               _stream(stream)), "rr_trace")
+    else:
+        _check(load().rr_trace_ex(scene.handle, _ptr(rays, "rays", torch.float32), n,
+                                  _ptr(count, "count", torch.int32, False), _ptr(hits, "hits", torch.float32),
+                                  int(refill), _stream(stream)), "rr_trace_ex")
     return hits
 
 
