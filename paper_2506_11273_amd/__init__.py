@@ -15,3 +15,6 @@ from .rr import (  # noqa: F401
     rr_compute_keys, rr_sort, rr_gather, rr_scatter_hits, rr_trace, rr_trace_profile, rr_reorder_and_trace,
     workspace,
 )
+from .batch import (  # noqa: F401
+    EXTRA_EXPORTS, RR_BATCH_EAGER, Batch, Server, load_tuned, save_tuned, segment, tuning_db_path,
+)

@@ -83,6 +83,7 @@ struct DeviceScene {
 
 rr_status launch_trace_stats(const DeviceScene& s, const rr_ray* rays, int64_t n_max, rr_hit* hits,
                              uint64_t* stats_dev, hipStream_t st);
+void trace_warm();
 rr_status launch_trace_refill(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
                               const uint32_t* count_dev, rr_hit* hits, uint32_t refill, hipStream_t st);
 rr_status launch_trace(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,

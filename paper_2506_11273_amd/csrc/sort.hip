@@ -1,16 +1,20 @@
 // Stable LSD radix sort of (key, index) pairs (Section 3.2 sorts key/index
-// pairs with a device-wide radix sort).
+// pairs with a device-wide radix sort), segmented: every segment is sorted
+// on its own, in place, and a plain sort is the one-segment case.
 //
 // Design (one histogram pass, then one scatter pass per digit):
-//  * k_sort_hist reads every key once and builds the digit histograms of
-//    all passes in LDS; k_sort_scan turns them into per-digit bases.
-//  * k_sort_pass takes tiles in launch order from an atomic counter, ranks
-//    the tile's keys by digit with wave64 ballots (a match over the digit's
-//    bits gives each lane its peers; the lowest peer bumps the wave's digit
-//    counter in LDS), publishes the tile's digit counts, looks back over the
-//    previous tiles' published counts for its global offsets (decoupled
-//    look-back, Merrill and Garland 2016), reorders the tile in LDS and
-//    writes each digit run contiguously.
+//  * segment descriptors live in device memory, so sizes can come from the
+//    device (a compaction count, a batch table) and one captured launch
+//    sequence serves any mix;
+//  * k_seg_hist reads every key once and builds the digit histograms of all
+//    passes per segment; k_seg_scan turns them into absolute digit bases;
+//  * k_seg_pass blocks are persistent and take tiles in order from an atomic
+//    counter.  A tile is ranked by digit with wave64 ballots (a match over
+//    the digit's bits gives each lane its peers; the lowest peer bumps the
+//    wave's digit counter in LDS), its digit counts are published, the
+//    previous tiles of the same segment are looked back for the global
+//    offsets (decoupled look-back, Merrill and Garland 2016), and the tile is
+//    reordered in LDS and written as contiguous digit runs.
 // Ranking keeps input order within a digit, so the sort is stable and the
 // output is the unique (key, index) lexicographic order for ascending input
 // indices.  Look-back waits are bounded: a wait that exceeds its limit sets
@@ -19,6 +23,7 @@
 #include <utility>
 
 #include "common.hpp"
+#include "sort_seg.hpp"
 
 namespace rr {
 namespace {
@@ -31,77 +36,125 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-__device__ __forceinline__ uint32_t read_count(const uint32_t* count_dev, uint32_t n_max) {
-  if (!count_dev) return n_max;
-  const uint32_t c = *count_dev;
-  return c < n_max ? c : n_max;
-}
-
-// Exclusive scan of one value per thread over a 256-thread block.
+// Exclusive scan of one value per thread over a 256-thread block (wave
+// shuffles, then the four wave totals); s needs kSortWaves words.
 __device__ __forceinline__ uint32_t block_scan_256(uint32_t v, uint32_t* s, uint32_t* total) {
-  const uint32_t t = threadIdx.x;
-  s[t] = v;
-  __syncthreads();
+  const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  uint32_t x = v;
 #pragma unroll
-  for (uint32_t off = 1; off < kSortThreads; off <<= 1) {
-    const uint32_t x = t >= off ? s[t - off] : 0u;
-    __syncthreads();
-    s[t] += x;
-    __syncthreads();
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, kWave);
+    if (lane >= (uint32_t)off) x += y;
   }
-  const uint32_t incl = s[t];
-  *total = s[kSortThreads - 1];
+  if (lane == kWave - 1) s[wave] = x;
   __syncthreads();
-  return incl - v;
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kSortWaves; ++w) {
+    const uint32_t t = s[w];
+    pre += (uint32_t)w < wave ? t : 0u;
+    tot += t;
+  }
+  *total = tot;
+  __syncthreads();
+  return pre + x - v;
 }
 
-__global__ void k_sort_init(uint32_t* __restrict__ hist, uint32_t n_hist, uint32_t* __restrict__ counters,
-                            uint32_t n_counters) {
-  for (uint32_t i = threadIdx.x; i < n_hist; i += blockDim.x) hist[i] = 0;
-  for (uint32_t i = threadIdx.x; i < n_counters; i += blockDim.x) counters[i] = 0;
+// Segment holding global tile t (segments ordered by tile_off).
+__device__ __forceinline__ uint32_t seg_of_tile(const SortSeg* segs, uint32_t nseg, uint32_t t) {
+  uint32_t lo = 0, hi = nseg;  // invariant: segs[lo].tile_off <= t
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (segs[mid].tile_off <= t) lo = mid;
+    else hi = mid;
+  }
+  return lo;
 }
 
-// Digit histograms of every pass, plus clearing of the look-back words the
-// passes will use.
-template <typename K, int DB>
-__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const K* __restrict__ keys, const uint32_t* count_dev,
-                                                            uint32_t n_max, uint32_t passes,
-                                                            uint32_t* __restrict__ hist,
-                                                            uint32_t* __restrict__ status, uint32_t tile_keys,
-                                                            uint32_t status_pass_stride) {
+// One segment of n = min(*count_dev, n_max) keys.
+__global__ void k_seg_setup_single(const uint32_t* count_dev, uint32_t n_max, uint32_t tile, SortHdr* hdr,
+                                   SortSeg* segs) {
+  if (threadIdx.x != 0) return;
+  uint32_t n = n_max;
+  if (count_dev) n = min(*count_dev, n_max);
+  const uint32_t tiles = (n + tile - 1) / tile;
+  segs[0] = SortSeg{0u, n, 0u, tiles};
+  *hdr = SortHdr{1u, tiles, n, 0u};
+}
+
+__global__ void k_seg_init(const SortHdr* hdr, uint32_t* __restrict__ hist, uint32_t words_per_seg,
+                           uint32_t* __restrict__ counters, uint32_t n_counters) {
+  const uint32_t n = hdr->nseg * words_per_seg;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) hist[i] = 0;
+  if (blockIdx.x == 0)
+    for (uint32_t i = threadIdx.x; i < n_counters; i += blockDim.x) counters[i] = 0;
+}
+
+// Digit histograms of every pass per segment (blocks take contiguous runs
+// of tiles, flushing their LDS counts when the segment changes), plus
+// clearing of the look-back words the passes will use.
+template <typename K, int DB, int KPT>
+__global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__ keys, const SortHdr* hdr,
+                                                           const SortSeg* __restrict__ segs, uint32_t passes,
+                                                           uint32_t* __restrict__ hist,
+                                                           uint32_t* __restrict__ status,
+                                                           uint32_t status_pass_stride) {
   constexpr uint32_t R = 1u << DB;
+  constexpr uint32_t kTile = kSortThreads * KPT;
   constexpr uint32_t kMaxPasses = (8 * sizeof(K) + DB - 1) / DB;
   __shared__ uint32_t s_h[kMaxPasses * R];
-  for (uint32_t i = threadIdx.x; i < passes * R; i += kSortThreads) s_h[i] = 0;
+  const uint32_t nseg = hdr->nseg, T = hdr->total_tiles;
+  const uint32_t words = passes * R;
+  for (uint32_t i = threadIdx.x; i < words; i += kSortThreads) s_h[i] = 0;
   __syncthreads();
-  const uint32_t n = read_count(count_dev, n_max);
-  const uint32_t stride = gridDim.x * kSortThreads;
-  for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < n; i += stride) {
-    const K k = keys[i];
-    for (uint32_t p = 0; p < passes; ++p) atomicAdd(&s_h[p * R + ((uint32_t)(k >> (p * DB)) & (R - 1))], 1u);
+  const uint32_t t0 = (uint32_t)(((uint64_t)blockIdx.x * T) / gridDim.x);
+  const uint32_t t1 = (uint32_t)(((uint64_t)(blockIdx.x + 1) * T) / gridDim.x);
+  uint32_t cur = t0 < t1 ? seg_of_tile(segs, nseg, t0) : 0u;
+  for (uint32_t t = t0; t < t1; ++t) {
+    uint32_t s = cur;
+    while (s + 1 < nseg && segs[s + 1].tile_off <= t) ++s;  // block-uniform
+    if (s != cur) {
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < words; i += kSortThreads) {
+        if (s_h[i]) atomicAdd(&hist[(size_t)cur * words + i], s_h[i]);
+        s_h[i] = 0;
+      }
+      __syncthreads();
+      cur = s;
+    }
+    const SortSeg sg = segs[s];
+    const uint32_t first = sg.off + (t - sg.tile_off) * kTile;
+    const uint32_t last = min(first + kTile, sg.off + sg.n);
+    for (uint32_t i = first + threadIdx.x; i < last; i += kSortThreads) {
+      const K k = keys[i];
+      for (uint32_t p = 0; p < passes; ++p) atomicAdd(&s_h[p * R + ((uint32_t)(k >> (p * DB)) & (R - 1))], 1u);
+    }
   }
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < passes * R; i += kSortThreads)
-    if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+  if (t0 < t1)
+    for (uint32_t i = threadIdx.x; i < words; i += kSortThreads)
+      if (s_h[i]) atomicAdd(&hist[(size_t)cur * words + i], s_h[i]);
   // clear the look-back words of the tiles this sort will use
-  const uint32_t tiles = (n + tile_keys - 1) / tile_keys;
-  const uint32_t words = tiles * R;
+  const uint32_t stride = gridDim.x * kSortThreads;
   for (uint32_t p = 0; p < passes; ++p)
-    for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < words; i += stride)
+    for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < T * R; i += stride)
       status[(size_t)p * status_pass_stride + i] = 0;
 }
 
-// hist[p][d] -> exclusive prefix over d (the first output slot of digit d).
+// hist[s][p][d] -> segment offset + exclusive prefix over d: the first
+// output slot of digit d in pass p.  One block per (segment, pass).
 template <int DB>
-__global__ __launch_bounds__(kSortThreads) void k_sort_scan(uint32_t* __restrict__ hist, uint32_t passes) {
+__global__ __launch_bounds__(kSortThreads) void k_seg_scan(const SortHdr* hdr, const SortSeg* __restrict__ segs,
+                                                           uint32_t passes, uint32_t* __restrict__ hist) {
   constexpr uint32_t R = 1u << DB;
-  __shared__ uint32_t s[kSortThreads];
-  for (uint32_t p = 0; p < passes; ++p) {
-    const uint32_t v = threadIdx.x < R ? hist[p * R + threadIdx.x] : 0u;
-    uint32_t total;
-    const uint32_t ex = block_scan_256(v, s, &total);
-    if (threadIdx.x < R) hist[p * R + threadIdx.x] = ex;
-  }
+  __shared__ uint32_t s[kSortWaves];
+  const uint32_t seg = blockIdx.x / passes, p = blockIdx.x % passes;
+  if (seg >= hdr->nseg) return;  // block-uniform
+  uint32_t* h = hist + ((size_t)seg * passes + p) * R;
+  const uint32_t v = threadIdx.x < R ? h[threadIdx.x] : 0u;
+  uint32_t total;
+  const uint32_t ex = block_scan_256(v, s, &total);
+  if (threadIdx.x < R) h[threadIdx.x] = segs[seg].off + ex;
 }
 
 template <typename K, int DB, int KPT>
@@ -113,194 +166,210 @@ struct PassSmem {
   uint32_t wave_hist[kSortWaves][R];
   uint32_t local_off[R];
   uint32_t global_off[R];
-  uint32_t scan[kSortThreads];
+  uint32_t scan[kSortWaves];
   uint32_t tile;
 };
 
 template <typename K, int DB, int KPT>
-__global__ __launch_bounds__(kSortThreads) void k_sort_pass(const K* __restrict__ keys_in,
-                                                            const uint32_t* __restrict__ idx_in,
-                                                            K* __restrict__ keys_out, uint32_t* __restrict__ idx_out,
-                                                            const uint32_t* count_dev, uint32_t n_max, uint32_t shift,
-                                                            const uint32_t* __restrict__ digit_base,
-                                                            uint32_t* __restrict__ status, uint32_t* tile_counter,
-                                                            uint32_t* err) {
+__global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__ keys_in,
+                                                           const uint32_t* __restrict__ idx_in,
+                                                           K* __restrict__ keys_out, uint32_t* __restrict__ idx_out,
+                                                           const SortHdr* hdr, const SortSeg* __restrict__ segs,
+                                                           uint32_t shift, uint32_t passes, uint32_t pass,
+                                                           const uint32_t* __restrict__ hist,
+                                                           uint32_t* __restrict__ status, uint32_t* tile_counter,
+                                                           uint32_t* err) {
   using S = PassSmem<K, DB, KPT>;
   constexpr uint32_t R = S::R;
   constexpr uint32_t kTile = S::kTile;
   __shared__ S sm;
   const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const uint32_t nseg = hdr->nseg, T = hdr->total_tiles;
 
-  if (tid == 0) sm.tile = atomicAdd(tile_counter, 1u);
-  for (uint32_t i = tid; i < kSortWaves * R; i += kSortThreads) (&sm.wave_hist[0][0])[i] = 0;
-  __syncthreads();
-  const uint32_t n = read_count(count_dev, n_max);
-  const uint32_t tile = sm.tile;
-  const uint32_t tiles = (n + kTile - 1) / kTile;
-  if (tile >= tiles) return;  // block-uniform
-  const uint32_t base = tile * kTile;
-  const uint32_t tile_n = min(kTile, n - base);
+  while (true) {
+    __syncthreads();  // the previous tile is fully written out
+    if (tid == 0) sm.tile = atomicAdd(tile_counter, 1u);
+    for (uint32_t i = tid; i < kSortWaves * R; i += kSortThreads) (&sm.wave_hist[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t tile = sm.tile;
+    if (tile >= T) break;  // block-uniform
+    const uint32_t s = seg_of_tile(segs, nseg, tile);
+    const SortSeg sg = segs[s];
+    const uint32_t tile_in = tile - sg.tile_off;
+    const uint32_t base = sg.off + tile_in * kTile;
+    const uint32_t tile_n = min(kTile, sg.n - tile_in * kTile);
+    const uint32_t* digit_base = hist + ((size_t)s * passes + pass) * R;
 
-  // ---- load (wave-striped: wave w owns KPT consecutive groups of 64)
-  K k[KPT];
-  uint32_t v[KPT];
-  uint32_t rank[KPT];
+    // ---- load (wave-striped: wave w owns KPT consecutive groups of 64)
+    K k[KPT];
+    uint32_t v[KPT];
+    uint32_t rank[KPT];
 #pragma unroll
-  for (int j = 0; j < KPT; ++j) {
-    const uint32_t pos = wave * (KPT * kWave) + j * kWave + lane;
-    const bool ok = pos < tile_n;
-    k[j] = ok ? keys_in[base + pos] : (K)0;
-    v[j] = ok ? idx_in[base + pos] : 0u;
-  }
-
-  // ---- rank within the wave, in (j, lane) order
-#pragma unroll
-  for (int j = 0; j < KPT; ++j) {
-    const uint32_t pos = wave * (KPT * kWave) + j * kWave + lane;
-    const bool ok = pos < tile_n;
-    const uint32_t d = (uint32_t)(k[j] >> shift) & (R - 1);
-    uint64_t peers = __ballot(ok);
-#pragma unroll
-    for (int b = 0; b < DB; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
+    for (int j = 0; j < KPT; ++j) {
+      const uint32_t pos = wave * (KPT * kWave) + j * kWave + lane;
+      const bool ok = pos < tile_n;
+      k[j] = ok ? keys_in[base + pos] : (K)0;
+      v[j] = ok ? idx_in[base + pos] : 0u;
     }
-    const uint32_t below = lanes_below(peers);
-    const int leader = ok ? (int)__builtin_ctzll(peers) : (int)lane;
-    uint32_t old = 0;
-    if (ok && (int)lane == leader) {
-      old = sm.wave_hist[wave][d];
-      sm.wave_hist[wave][d] = old + (uint32_t)__popcll(peers);
-    }
-    old = __shfl(old, leader, kWave);
-    rank[j] = old + below;
-  }
-  __syncthreads();
 
-  // ---- per digit: wave offsets, tile count, publication
-  uint32_t count = 0;
-  for (uint32_t d = tid; d < R; d += kSortThreads) {
-    uint32_t c = 0;
+    // ---- rank within the wave, in (j, lane) order
 #pragma unroll
-    for (int w = 0; w < kSortWaves; ++w) {
-      const uint32_t t = sm.wave_hist[w][d];
-      sm.wave_hist[w][d] = c;
-      c += t;
-    }
-    count = c;
-    const uint32_t word = (tile == 0 ? kStatusPrefix : kStatusAggregate) | c;
-    __hip_atomic_store(&status[(size_t)tile * R + d], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  uint32_t total;
-  const uint32_t local = block_scan_256(tid < R ? count : 0u, sm.scan, &total);
-  if (tid < R) sm.local_off[tid] = local;
-
-  // ---- decoupled look-back: sum the counts of digit d in earlier tiles
-  if (tid < R) {
-    const uint32_t d = tid;
-    uint32_t prefix = 0;
-    if (tile > 0) {
-      int32_t j = (int32_t)tile - 1;
-      uint32_t spins = 0;
-      while (j >= 0) {
-        const uint32_t w =
-            __hip_atomic_load(&status[(size_t)j * R + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t flag = w & ~kStatusCountMask;
-        if (flag == 0) {
-          if (++spins > kSpinLimit) {
-            atomicOr(err, 1u);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        prefix += w & kStatusCountMask;
-        if (flag == kStatusPrefix) break;
-        --j;
-      }
-      __hip_atomic_store(&status[(size_t)tile * R + d], kStatusPrefix | (prefix + count), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    }
-    sm.global_off[d] = digit_base[d] + prefix;
-  }
-  __syncthreads();
-
-  // ---- reorder the tile in LDS by digit
-#pragma unroll
-  for (int j = 0; j < KPT; ++j) {
-    const uint32_t pos = wave * (KPT * kWave) + j * kWave + lane;
-    if (pos < tile_n) {
+    for (int j = 0; j < KPT; ++j) {
+      const uint32_t pos = wave * (KPT * kWave) + j * kWave + lane;
+      const bool ok = pos < tile_n;
       const uint32_t d = (uint32_t)(k[j] >> shift) & (R - 1);
-      const uint32_t at = sm.local_off[d] + sm.wave_hist[wave][d] + rank[j];
-      if (at < kTile) {
-        sm.keys[at] = k[j];
-        sm.idx[at] = v[j];
+      uint64_t peers = __ballot(ok);
+#pragma unroll
+      for (int b = 0; b < DB; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      const uint32_t below = lanes_below(peers);
+      const int leader = ok ? (int)__builtin_ctzll(peers) : (int)lane;
+      uint32_t old = 0;
+      if (ok && (int)lane == leader) {
+        old = sm.wave_hist[wave][d];
+        sm.wave_hist[wave][d] = old + (uint32_t)__popcll(peers);
+      }
+      old = __shfl(old, leader, kWave);
+      rank[j] = old + below;
+    }
+    __syncthreads();
+
+    // ---- per digit: wave offsets, tile count, publication
+    uint32_t count = 0;
+    for (uint32_t d = tid; d < R; d += kSortThreads) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int w = 0; w < kSortWaves; ++w) {
+        const uint32_t t = sm.wave_hist[w][d];
+        sm.wave_hist[w][d] = c;
+        c += t;
+      }
+      count = c;
+      const uint32_t word = (tile_in == 0 ? kStatusPrefix : kStatusAggregate) | c;
+      __hip_atomic_store(&status[(size_t)tile * R + d], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    uint32_t total;
+    const uint32_t local = block_scan_256(tid < R ? count : 0u, sm.scan, &total);
+    if (tid < R) sm.local_off[tid] = local;
+
+    // ---- decoupled look-back over this segment's earlier tiles
+    if (tid < R) {
+      const uint32_t d = tid;
+      uint32_t prefix = 0;
+      if (tile_in > 0) {
+        int64_t j = (int64_t)tile - 1;
+        uint32_t spins = 0;
+        while (j >= (int64_t)sg.tile_off) {
+          const uint32_t w =
+              __hip_atomic_load(&status[(size_t)j * R + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const uint32_t flag = w & ~kStatusCountMask;
+          if (flag == 0) {
+            if (++spins > kSpinLimit) {
+              atomicOr(err, 1u);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+          }
+          prefix += w & kStatusCountMask;
+          if (flag == kStatusPrefix) break;
+          --j;
+        }
+        __hip_atomic_store(&status[(size_t)tile * R + d], kStatusPrefix | (prefix + count), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+      sm.global_off[d] = digit_base[d] + prefix;
+    }
+    __syncthreads();
+
+    // ---- reorder the tile in LDS by digit
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      const uint32_t pos = wave * (KPT * kWave) + j * kWave + lane;
+      if (pos < tile_n) {
+        const uint32_t d = (uint32_t)(k[j] >> shift) & (R - 1);
+        const uint32_t at = sm.local_off[d] + sm.wave_hist[wave][d] + rank[j];
+        if (at < kTile) {
+          sm.keys[at] = k[j];
+          sm.idx[at] = v[j];
+        }
       }
     }
-  }
-  __syncthreads();
+    __syncthreads();
 
-  // ---- write digit runs contiguously
-  for (uint32_t p = tid; p < tile_n; p += kSortThreads) {
-    const K key = sm.keys[p];
-    const uint32_t d = (uint32_t)(key >> shift) & (R - 1);
-    const uint32_t out = sm.global_off[d] + (p - sm.local_off[d]);
-    if (out < n) {  // always true when the histograms are consistent
-      keys_out[out] = key;
-      idx_out[out] = sm.idx[p];
+    // ---- write digit runs contiguously
+    const uint32_t seg_end = sg.off + sg.n;
+    for (uint32_t p = tid; p < tile_n; p += kSortThreads) {
+      const K key = sm.keys[p];
+      const uint32_t d = (uint32_t)(key >> shift) & (R - 1);
+      const uint32_t out = sm.global_off[d] + (p - sm.local_off[d]);
+      if (out < seg_end) {  // always true when the histograms are consistent
+        keys_out[out] = key;
+        idx_out[out] = sm.idx[p];
+      }
     }
   }
 }
 
-struct Layout {
-  size_t keys_alt, idx_alt, hist, counters, status, total;
-  uint32_t passes, tile, status_stride;
-};
-
-Layout layout_for(int64_t n_max, uint32_t key_bits, uint32_t db, uint32_t kpt) {
-  Layout L{};
-  const size_t kb = key_bits / 8;
-  L.passes = (key_bits + db - 1) / db;
-  L.tile = kSortThreads * kpt;
-  const size_t tiles = (size_t)((n_max + L.tile - 1) / L.tile) + 1;
-  const size_t R = (size_t)1 << db;
-  L.status_stride = (uint32_t)(tiles * R);
-  size_t off = 0;
-  L.keys_alt = off; off = align_up(off + kb * (size_t)n_max, 256);
-  L.idx_alt = off; off = align_up(off + 4 * (size_t)n_max, 256);
-  L.hist = off; off = align_up(off + 4 * L.passes * R, 256);
-  L.counters = off; off = align_up(off + 4 * (L.passes + 1), 256);  // tile counters, then the error word
-  L.status = off; off = align_up(off + 4 * (size_t)L.passes * L.status_stride, 256);
-  L.total = off;
-  return L;
+template <typename F>
+uint32_t resident(F kernel, int threads) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per <= 0) per = 1;
+  return (uint32_t)(cus * per);
 }
 
 template <typename K, int DB, int KPT>
-rr_status sort_impl(K* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, char* ws, const Layout& L,
-                    hipStream_t st) {
+struct Resident {
+  static uint32_t hist() {
+    static const uint32_t v = resident(k_seg_hist<K, DB, KPT>, kSortThreads);
+    return v;
+  }
+  static uint32_t pass() {
+    static const uint32_t v = resident(k_seg_pass<K, DB, KPT>, kSortThreads);
+    return v;
+  }
+};
+
+template <typename K, int DB, int KPT>
+rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, SortHdr* hdr_ext, SortSeg* segs_ext,
+                        const uint32_t* count_dev, uint32_t n_max, hipStream_t st) {
   constexpr uint32_t R = 1u << DB;
   K* kalt = reinterpret_cast<K*>(ws + L.keys_alt);
   uint32_t* ialt = reinterpret_cast<uint32_t*>(ws + L.idx_alt);
+  const bool single = hdr_ext == nullptr;
+  SortHdr* hdr = single ? reinterpret_cast<SortHdr*>(ws + L.hdr) : hdr_ext;
+  SortSeg* segs = single ? reinterpret_cast<SortSeg*>(ws + L.segs) : segs_ext;
   uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
   uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
   uint32_t* err = counters + L.passes;
   uint32_t* status = reinterpret_cast<uint32_t*>(ws + L.status);
-  const uint32_t n = (uint32_t)n_max;
-  const uint32_t tiles = (n + L.tile - 1) / L.tile;
 
-  hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, st, hist, L.passes * R, counters, L.passes + 1);
-  const uint32_t hist_blocks = std::max(1u, std::min(tiles, 2048u));
-  hipLaunchKernelGGL((k_sort_hist<K, DB>), dim3(hist_blocks), dim3(kSortThreads), 0, st, keys, count_dev, n,
-                     L.passes, hist, status, L.tile, L.status_stride);
-  hipLaunchKernelGGL((k_sort_scan<DB>), dim3(1), dim3(kSortThreads), 0, st, hist, L.passes);
+  const uint32_t hist_res = Resident<K, DB, KPT>::hist();
+  const uint32_t pass_res = Resident<K, DB, KPT>::pass();
+  const uint32_t max_tiles = L.max_tiles;
+  if (single)
+    hipLaunchKernelGGL(k_seg_setup_single, dim3(1), dim3(64), 0, st, count_dev, n_max, L.tile, hdr, segs);
+  hipLaunchKernelGGL(k_seg_init, dim3(std::max(1u, std::min(64u, L.max_seg))), dim3(256), 0, st, hdr, hist,
+                     L.passes * R, counters, L.passes + 1);
+  const uint32_t hist_blocks = std::max(1u, std::min(max_tiles, std::min(hist_res, 2048u)));
+  hipLaunchKernelGGL((k_seg_hist<K, DB, KPT>), dim3(hist_blocks), dim3(kSortThreads), 0, st, keys, hdr, segs,
+                     L.passes, hist, status, L.status_stride);
+  hipLaunchKernelGGL((k_seg_scan<DB>), dim3(L.max_seg * L.passes), dim3(kSortThreads), 0, st, hdr, segs, L.passes,
+                     hist);
+  const uint32_t pass_blocks = std::max(1u, std::min(max_tiles, pass_res));
   K* src_k = keys;
   uint32_t* src_i = idx;
   K* dst_k = kalt;
   uint32_t* dst_i = ialt;
   for (uint32_t p = 0; p < L.passes; ++p) {
-    hipLaunchKernelGGL((k_sort_pass<K, DB, KPT>), dim3(tiles), dim3(kSortThreads), 0, st, src_k, src_i, dst_k,
-                       dst_i, count_dev, n, p * DB, hist + p * R, status + (size_t)p * L.status_stride,
+    hipLaunchKernelGGL((k_seg_pass<K, DB, KPT>), dim3(pass_blocks), dim3(kSortThreads), 0, st, src_k, src_i, dst_k,
+                       dst_i, hdr, segs, p * DB, L.passes, p, hist, status + (size_t)p * L.status_stride,
                        counters + p, err);
     std::swap(src_k, dst_k);
     std::swap(src_i, dst_i);
@@ -312,12 +381,34 @@ rr_status sort_impl(K* keys, uint32_t* idx, int64_t n_max, const uint32_t* count
 
 }  // namespace
 
+SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_t db, uint32_t kpt) {
+  SegLayout L{};
+  const size_t kb = key_bits / 8;
+  L.passes = (key_bits + db - 1) / db;
+  L.tile = kSortThreads * kpt;
+  L.max_seg = max_seg;
+  // each segment can add one partial tile
+  L.max_tiles = (uint32_t)((n_max + L.tile - 1) / L.tile + max_seg);
+  const size_t R = (size_t)1 << db;
+  L.status_stride = (uint32_t)(L.max_tiles * R);
+  size_t off = 0;
+  L.keys_alt = off; off = align_up(off + kb * (size_t)n_max, 256);
+  L.idx_alt = off; off = align_up(off + 4 * (size_t)n_max, 256);
+  L.hdr = off; off = align_up(off + sizeof(SortHdr), 256);
+  L.segs = off; off = align_up(off + sizeof(SortSeg) * max_seg, 256);
+  L.hist = off; off = align_up(off + 4 * (size_t)max_seg * L.passes * R, 256);
+  L.counters = off; off = align_up(off + 4 * (L.passes + 1), 256);  // tile counters, then the error word
+  L.status = off; off = align_up(off + 4 * (size_t)L.passes * L.status_stride, 256);
+  L.total = off;
+  return L;
+}
+
 bool sort_config_supported(uint32_t key_bits, uint32_t digit_bits, uint32_t kpt) {
   return (key_bits == 32 || key_bits == 64) && (digit_bits == 4 || digit_bits == 8) && (kpt == 8 || kpt == 16);
 }
 
 size_t sort_workspace_bytes(int64_t n_max, uint32_t key_bits, uint32_t digit_bits, uint32_t kpt) {
-  return layout_for(n_max, key_bits, digit_bits, kpt).total;
+  return seg_layout(n_max, 1, key_bits, digit_bits, kpt).total;
 }
 
 size_t sort_workspace_bytes_any(int64_t n_max, uint32_t key_bits) {
@@ -327,15 +418,30 @@ size_t sort_workspace_bytes_any(int64_t n_max, uint32_t key_bits) {
   return m;
 }
 
-rr_status launch_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
-                      uint32_t db, uint32_t kpt, void* ws, size_t ws_bytes, hipStream_t st) {
-  if (!sort_config_supported(key_bits, db, kpt)) return RR_ERR_UNSUPPORTED;
-  const Layout L = layout_for(n_max, key_bits, db, kpt);
-  if (ws_bytes < L.total) return RR_ERR_WORKSPACE_TOO_SMALL;
+void sort_warm(uint32_t key_bits, uint32_t db, uint32_t kpt) {
+#define RR_WARM_CASE(KT, DBV, KPTV)                                  \
+  if (sizeof(KT) * 8 == key_bits && db == DBV && kpt == KPTV) {      \
+    (void)Resident<KT, DBV, KPTV>::hist();                           \
+    (void)Resident<KT, DBV, KPTV>::pass();                           \
+  }
+  RR_WARM_CASE(uint32_t, 8, 16)
+  RR_WARM_CASE(uint32_t, 8, 8)
+  RR_WARM_CASE(uint32_t, 4, 16)
+  RR_WARM_CASE(uint32_t, 4, 8)
+  RR_WARM_CASE(uint64_t, 8, 16)
+  RR_WARM_CASE(uint64_t, 8, 8)
+  RR_WARM_CASE(uint64_t, 4, 16)
+  RR_WARM_CASE(uint64_t, 4, 8)
+#undef RR_WARM_CASE
+}
+
+rr_status launch_seg_sort(void* keys, uint32_t* idx, const SegLayout& L, void* ws, SortHdr* hdr, SortSeg* segs,
+                          const uint32_t* count_dev, uint32_t n_max, uint32_t key_bits, uint32_t db, uint32_t kpt,
+                          hipStream_t st) {
   char* w = reinterpret_cast<char*>(ws);
-#define RR_SORT_CASE(KT, DBV, KPTV)                                                                   \
-  if (sizeof(KT) * 8 == key_bits && db == DBV && kpt == KPTV)                                       \
-    return sort_impl<KT, DBV, KPTV>(reinterpret_cast<KT*>(keys), idx, n_max, count_dev, w, L, st);
+#define RR_SORT_CASE(KT, DBV, KPTV)                                                                        \
+  if (sizeof(KT) * 8 == key_bits && db == DBV && kpt == KPTV)                                            \
+    return seg_sort_impl<KT, DBV, KPTV>(reinterpret_cast<KT*>(keys), idx, L, w, hdr, segs, count_dev, n_max, st);
   RR_SORT_CASE(uint32_t, 8, 16)
   RR_SORT_CASE(uint32_t, 8, 8)
   RR_SORT_CASE(uint32_t, 4, 16)
@@ -346,6 +452,14 @@ rr_status launch_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* 
   RR_SORT_CASE(uint64_t, 4, 8)
 #undef RR_SORT_CASE
   return RR_ERR_UNSUPPORTED;
+}
+
+rr_status launch_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                      uint32_t db, uint32_t kpt, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (!sort_config_supported(key_bits, db, kpt)) return RR_ERR_UNSUPPORTED;
+  const SegLayout L = seg_layout(n_max, 1, key_bits, db, kpt);
+  if (ws_bytes < L.total) return RR_ERR_WORKSPACE_TOO_SMALL;
+  return launch_seg_sort(keys, idx, L, ws, nullptr, nullptr, count_dev, (uint32_t)n_max, key_bits, db, kpt, st);
 }
 
 }  // namespace rr

@@ -1,0 +1,37 @@
+// Device-side descriptors and workspace layout of the segmented radix sort.
+#pragma once
+
+#include "common.hpp"
+
+namespace rr {
+
+// One segment: keys [off, off + n) of the key array, its tiles starting at
+// global tile index tile_off.  Segments are listed in increasing off and
+// tile_off order.
+struct SortSeg {
+  uint32_t off, n, tile_off, ntiles;
+};
+
+struct SortHdr {
+  uint32_t nseg, total_tiles, total_keys, pad;
+};
+
+struct SegLayout {
+  size_t keys_alt, idx_alt, hdr, segs, hist, counters, status, total;
+  uint32_t passes, tile, max_seg, max_tiles, status_stride;
+};
+
+SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_t db, uint32_t kpt);
+
+// Sorts every segment described by the device header and segment table
+// hdr / segs.  With hdr == nullptr one segment of min(*count_dev, n_max)
+// keys (n_max without count_dev) is set up on the device, in the workspace.
+rr_status launch_seg_sort(void* keys, uint32_t* idx, const SegLayout& L, void* ws, SortHdr* hdr, SortSeg* segs,
+                          const uint32_t* count_dev, uint32_t n_max, uint32_t key_bits, uint32_t db, uint32_t kpt,
+                          hipStream_t st);
+
+// Runs the one-time occupancy queries of a sort configuration, so that a
+// later stream capture records kernel launches only.
+void sort_warm(uint32_t key_bits, uint32_t db, uint32_t kpt);
+
+}  // namespace rr

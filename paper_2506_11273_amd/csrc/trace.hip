@@ -295,6 +295,11 @@ rr_status launch_trace_refill(const DeviceScene& s, const rr_ray* rays, const ui
   return launch4<false>(s, rays, idx, n_max, count_dev, hits, refill, nullptr, st);
 }
 
+void trace_warm() {
+  (void)resident_blocks<false>();
+  (void)resident_blocks<true>();
+}
+
 rr_status launch_trace_stats(const DeviceScene& s, const rr_ray* rays, int64_t n_max, rr_hit* hits,
                              uint64_t* stats_dev, hipStream_t st) {
   return launch4<true>(s, rays, nullptr, n_max, nullptr, hits, kDefaultRefill,

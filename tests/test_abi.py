@@ -10,9 +10,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_symbols():
-    text = open(os.path.join(ROOT, "include", "rr.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(rr_[a-z_0-9]+)\s*\(", text)))
+    syms = set()
+    for h in ("rr.h", "rr_batch.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        syms |= set(re.findall(r"\b(rr_[a-z_0-9]+)\s*\(", text))
+    return sorted(syms)
 
 
 @pytest.fixture(scope="module")
@@ -23,7 +26,8 @@ def lib():
 
 def test_header_declares_the_path():
     syms = declared_symbols()
-    for s in ("rr_compute_keys", "rr_sort", "rr_gather", "rr_trace", "rr_reorder_and_trace"):
+    for s in ("rr_compute_keys", "rr_sort", "rr_gather", "rr_trace", "rr_reorder_and_trace", "rr_batch_run",
+              "rr_server_submit"):
         assert s in syms
 
 

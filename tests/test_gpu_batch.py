@@ -1,0 +1,257 @@
+"""GPU tests of the batched and serving layers.
+
+Invariants: every segment of a batch gives exactly the results of the
+per-call path on that wavefront alone (hits bit for bit, permutation equal to
+the oracle's stable order); every launch shape gives the same results; the
+captured graph replayed many times (with eager work and synchronisations in
+between) matches the eager launches; a served request's hits equal the
+request traced alone, whatever else was in flight.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def rr():
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    import paper_2506_11273_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def city(rr):
+    w = W.city_small(seed=21, width=200, height=120, depth=1, n=16, n_clutter=20000)
+    scene = rr.Scene(w.tris)
+    yield w, scene
+    scene.close()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+KINDS = [(0, 32), (1, 32), (1, 64), (2, 32), (2, 64)]
+
+
+def make_segments(rr, w, scene, sizes, seed=0):
+    """Segments cut from a pool of rays, each with its own key method."""
+    lo, hi = scene.bounds()
+    rng = np.random.default_rng(seed)
+    pool = w.rays
+    out = []
+    for k, n in enumerate(sizes):
+        idx = rng.integers(0, pool.shape[0], n)
+        rays = to_dev(pool[idx]) if n else torch.empty((0, 8), dtype=torch.float32, device=DEV)
+        kind, bits = KINDS[k % len(KINDS)]
+        out.append({"rays": rays, "rays_np": pool[idx], "key": rr.key_params(kind, bits, lo, hi, 0.25),
+                    "kind": kind, "bits": bits, "lo": lo, "hi": hi,
+                    "hits": torch.empty((n, 4), dtype=torch.float32, device=DEV),
+                    "perm": torch.empty(max(n, 1), dtype=torch.int32, device=DEV)})
+    return out
+
+
+def seg_structs(rr, segs):
+    return [rr.segment(s["rays"], s["hits"], s["key"], perm=s["perm"], n=s["rays"].shape[0]) for s in segs]
+
+
+def expected(rr, scene, s):
+    """Per-call results on the segment alone: hits in ray order and the
+    oracle's stable permutation."""
+    n = s["rays"].shape[0]
+    hits = rr.hits_to_numpy(rr.rr_trace(scene, s["rays"])) if n else np.empty(0, O.HIT_DTYPE)
+    if s["kind"] == 0:
+        perm = np.arange(n, dtype=np.uint32)
+    else:
+        k = O.keys(s["rays_np"], s["kind"], s["bits"], s["lo"], s["hi"], 0.25)
+        _, perm = O.sort_pairs(k)
+    return hits, perm
+
+
+def check(rr, scene, segs, what=""):
+    torch.cuda.synchronize()
+    for j, s in enumerate(segs):
+        n = s["rays"].shape[0]
+        hits, perm = expected(rr, scene, s)
+        got = rr.hits_to_numpy(s["hits"][:n])
+        assert got.tobytes() == hits.tobytes(), f"{what} segment {j} hits"
+        assert np.array_equal(s["perm"][:n].cpu().numpy().view(np.uint32), perm), f"{what} segment {j} perm"
+
+
+SIZES = [5000, 0, 1, 4097, 30000, 777, 65536, 12345, 2, 100000]
+
+
+def test_batch_equals_per_call(rr, city):
+    w, scene = city
+    segs = make_segments(rr, w, scene, SIZES, seed=1)
+    with rr.Batch(scene, max_rays=sum(SIZES), max_segments=16) as b:
+        b.run(seg_structs(rr, segs))
+        check(rr, scene, segs, "graph")
+        for s in segs:
+            s["hits"].fill_(7.0)
+        b.run(seg_structs(rr, segs), flags=rr.RR_HITS_ORIGINAL_ORDER | rr.RR_BATCH_EAGER)
+        check(rr, scene, segs, "eager")
+
+
+def test_batch_all_32bit_keys_and_sorted_order_hits(rr, city):
+    w, scene = city
+    segs = make_segments(rr, w, scene, [3000, 9000, 20000], seed=2)
+    lo, hi = scene.bounds()
+    for s in segs:
+        s["key"] = rr.key_params(1, 32, lo, hi)
+        s["kind"], s["bits"] = 1, 32
+    with rr.Batch(scene, max_rays=40000, max_segments=4) as b:
+        b.run(seg_structs(rr, segs), flags=0)
+        torch.cuda.synchronize()
+        for s in segs:
+            hits, perm = expected(rr, scene, s)
+            got = rr.hits_to_numpy(s["hits"])
+            assert got.tobytes() == hits[perm].tobytes()  # sorted order = ray order through perm
+
+
+def test_graph_replays_match_eager(rr, city):
+    w, scene = city
+    segs = make_segments(rr, w, scene, [20000, 3000, 50000, 1], seed=3)
+    with rr.Batch(scene, max_rays=80000, max_segments=8) as b:
+        b.run(seg_structs(rr, segs), flags=rr.RR_HITS_ORIGINAL_ORDER | rr.RR_BATCH_EAGER)
+        torch.cuda.synchronize()
+        ref = [(s["hits"].clone(), s["perm"].clone()) for s in segs]
+        for rep in range(5):
+            for s in segs:
+                s["hits"].zero_()
+                s["perm"].zero_()
+            torch.cuda.synchronize()
+            b.run(seg_structs(rr, segs))
+            torch.cuda.synchronize()
+            for (h, p), s in zip(ref, segs):
+                assert torch.equal(s["hits"].view(torch.int32), h.view(torch.int32)), rep
+                assert torch.equal(s["perm"], p), rep
+            # unrelated eager work between replays
+            x = torch.randn(1 << 16, device=DEV)
+            assert float(x.sum()) == pytest.approx(float(x.cpu().sum()), rel=1e-3, abs=1e-2)
+
+
+def test_batch_mix_changes_between_runs(rr, city):
+    w, scene = city
+    with rr.Batch(scene, max_rays=200000, max_segments=16) as b:
+        for seed, sizes in enumerate([[1000, 2000], [150000, 3, 40000], [64], [0, 0, 5000]]):
+            segs = make_segments(rr, w, scene, sizes, seed=10 + seed)
+            b.run(seg_structs(rr, segs))
+            check(rr, scene, segs, f"mix {seed}")
+
+
+def test_every_launch_shape_gives_identical_results(rr, city):
+    w, scene = city
+    segs = make_segments(rr, w, scene, [30000, 7000, 60000], seed=4)
+    with rr.Batch(scene, max_rays=100000, max_segments=4) as b:
+        outs = []
+        for db in (8, 4):
+            for kpt in (16, 8):
+                for refill in (1, 16, 64):
+                    b.set_config({"digit_bits": db, "keys_per_thread": kpt, "refill": refill})
+                    b.run(seg_structs(rr, segs))
+                    torch.cuda.synchronize()
+                    outs.append([(s["hits"].cpu().numpy().tobytes(), s["perm"].cpu().numpy().tobytes())
+                                 for s in segs])
+        assert all(o == outs[0] for o in outs)
+        best, ms = b.autotune(seg_structs(rr, segs), reps=2)
+        assert best["digit_bits"] in (4, 8) and ms > 0
+        b.run(seg_structs(rr, segs))
+        check(rr, scene, segs, "tuned")
+
+
+def test_batch_rejects_bad_input(rr, city):
+    w, scene = city
+    segs = make_segments(rr, w, scene, [1000, 1000], seed=5)
+    with rr.Batch(scene, max_rays=1500, max_segments=1) as b:
+        with pytest.raises(rr.RRError):
+            b.run(seg_structs(rr, segs))          # more segments than the batch holds
+    with rr.Batch(scene, max_rays=1500, max_segments=4) as b:
+        with pytest.raises(rr.RRError) as e:
+            b.run(seg_structs(rr, segs))          # more rays than the capacity
+        assert e.value.status == -6
+
+
+# ---------------------------------------------------------------- serving
+
+def test_server_results_equal_alone_and_overlap(rr, city):
+    w, scene = city
+    rng = np.random.default_rng(6)
+    sizes = [int(x) for x in np.exp(rng.uniform(np.log(500), np.log(60000), 24))]
+    segs = make_segments(rr, w, scene, sizes, seed=6)
+    with rr.Server(scene, slots=3, hbm_budget_bytes=8 << 30, max_batch_rays=150000, max_batch_requests=8) as sv:
+        sv.start()
+        ids = []
+        for k, s in enumerate(segs):
+            ids.append(sv.submit(s["rays"], s["hits"], s["key"], arrival_s=0.002 * k))
+        sv.drain(120.0)
+        st = [sv.wait(i) for i in ids]
+        stats = sv.stats()
+    assert all(x["status"] == 0 and x["done"] for x in st)
+    assert stats["completed"] == len(segs) and stats["failed"] == 0
+    assert stats["p99_ms"] >= stats["p50_ms"] > 0 and stats["rays"] == sum(sizes)
+    # each request's hits equal the request traced alone
+    for j, s in enumerate(segs):
+        hits, _ = expected(rr, scene, s)
+        assert rr.hits_to_numpy(s["hits"]).tobytes() == hits.tobytes(), j
+    # latency is measured from arrival, and nothing starts before it arrives
+    for x in st:
+        assert x["start_s"] >= x["arrival_s"] - 1e-6 and x["finish_s"] >= x["start_s"]
+
+
+def test_server_batches_and_overlaps_under_load(rr, city):
+    w, scene = city
+    sizes = [40000] * 16
+    segs = make_segments(rr, w, scene, sizes, seed=7)
+    with rr.Server(scene, slots=2, hbm_budget_bytes=8 << 30, max_batch_rays=120000, max_batch_requests=4) as sv:
+        sv.start()
+        ids = [sv.submit(s["rays"], s["hits"], s["key"], arrival_s=0.0) for s in segs]
+        sv.drain(120.0)
+        st = [sv.wait(i) for i in ids]
+        stats = sv.stats()
+    assert max(x["batch_requests"] for x in st) > 1          # requests were batched together
+    assert stats["batches"] < len(segs)
+    # two batches were on the device at the same time
+    spans = sorted({(x["start_s"], x["finish_s"]) for x in st})
+    assert any(b[0] < a[1] for a, b in zip(spans, spans[1:]))
+    for j, s in enumerate(segs):
+        hits, _ = expected(rr, scene, s)
+        assert rr.hits_to_numpy(s["hits"]).tobytes() == hits.tobytes(), j
+
+
+def test_server_admission_and_rejection(rr, city):
+    w, scene = city
+    # a budget too small for one slot
+    with pytest.raises(rr.RRError) as e:
+        rr.Server(scene, slots=1, hbm_budget_bytes=1 << 20, max_batch_rays=100000)
+    assert e.value.status == -6
+    segs = make_segments(rr, w, scene, [5000, 200000, 3000], seed=8)
+    with rr.Server(scene, slots=1, hbm_budget_bytes=8 << 30, max_batch_rays=100000) as sv:
+        sv.start()
+        a = sv.submit(segs[0]["rays"], segs[0]["hits"], segs[0]["key"])
+        with pytest.raises(rr.RRError) as e:
+            sv.submit(segs[1]["rays"], segs[1]["hits"], segs[1]["key"])   # larger than any batch
+        assert e.value.status == -6
+        host = torch.zeros((10, 8))
+        lib = rr.load()
+        import ctypes
+        rid = ctypes.c_int64()
+        bad = lib.rr_server_submit(sv.handle, host.data_ptr(), 10, ctypes.byref(segs[0]["key"]),
+                                   segs[0]["hits"].data_ptr(), 1, -1.0, ctypes.byref(rid))
+        assert bad == -1                                                   # host memory refused at submit
+        c = sv.submit(segs[2]["rays"], segs[2]["hits"], segs[2]["key"])
+        sv.drain(60.0)
+        assert sv.wait(a)["status"] == 0 and sv.wait(c)["status"] == 0
+        assert sv.stats()["rejected"] == 1
+    for s in (segs[0], segs[2]):
+        hits, _ = expected(rr, scene, s)
+        assert rr.hits_to_numpy(s["hits"]).tobytes() == hits.tobytes()
