@@ -1,21 +1,27 @@
 """Benchmark of the reordering hot path on one MI355X.
 
-Workload: the 1920x1080 bounce-2 diffuse wavefront (2,073,600 rays) on the
-~1M-triangle grid city, resident in HBM.  One step is the whole reordered
-path on that wavefront through the C ABI: Two Point 64-bit keys
+Headline workload: the 1920x1080 bounce-2 diffuse wavefront (2,073,600 rays)
+on the ~1M-triangle grid city, resident in HBM.  One step is the whole
+reordered path on that wavefront through the C ABI: Two Point 64-bit keys
 (rr_compute_keys), the key/index sort (rr_sort), the ray gather (rr_gather)
 and the closest-hit trace of the sorted rays (rr_trace).  HIP events on the
-working stream bracket each phase inside the timed region; the unsorted
-trace of the same rays is timed the same way for the comparison.
+working stream bracket each phase inside the timed region; the unsorted trace
+of the same rays is timed the same way for the comparison.
 
-Prints one JSON line: MRays/s including the reorder overhead (value), the
-unsorted trace MRays/s, per-phase milliseconds, the sort's bandwidth, the
-trace kernel's roofline figures and the CPU oracle's rate on the host cores.
+Further sections (each can be skipped): the fused entry point per key
+variant; the 3840x2160 bounce-3 wavefront (8,294,400 slots, terminated rays
+compacted before the sort); 64 wavefronts of mixed bounces reordered and
+traced in one graph launch with autotuned launch shape; a Poisson stream of
+requests served with continuous batching on the ~4M-triangle city, with
+p50/p99 latency; and the CPU oracle on the host cores.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -28,6 +34,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MRays/s incl. reorder vs unsorted trace; sort GB/s; p50/p99 batch latency"
+KEYS = {"none": (0, 32), "od32": (1, 32), "od64": (1, 64), "ot32": (2, 32), "ot64": (2, 64)}
+SECTIONS = ("variants", "bounce3", "batch", "serve", "cpu")
 
 
 def parse():
@@ -35,18 +43,25 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--key", default="ot64", choices=["od32", "od64", "ot32", "ot64"])
+    ap.add_argument("--key", default="ot64", choices=[k for k in KEYS if k != "none"])
     ap.add_argument("--builder", type=int, default=1, help="0 median split, 1 binned SAH")
+    ap.add_argument("--skip", default="", help="comma list of sections to skip: " + ",".join(SECTIONS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variants", action="store_true", help="skip the other key variants")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
+                    help="offered loads, fractions of the measured batched capacity")
     ap.add_argument("--phases", default="all", choices=["all", "trace"],
                     help="'trace' times only the sorted and unsorted traces (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
-    return ap.parse_args()
-
-
-KEYS = {"od32": (1, 32), "od64": (1, 64), "ot32": (2, 32), "ot64": (2, 64)}
+    a = ap.parse_args()
+    a.skip = set(s for s in a.skip.split(",") if s)
+    if a.no_cpu_baseline:
+        a.skip.add("cpu")
+    if a.no_variants:
+        a.skip.add("variants")
+    return a
 
 
 def sort_algorithmic_bytes(n: int, key_bits: int) -> int:
@@ -56,11 +71,21 @@ def sort_algorithmic_bytes(n: int, key_bits: int) -> int:
     return n * (k + (key_bits // 8) * 2 * (k + 4))
 
 
+def median_ms(torch, stream, fn, reps):
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps)]
+    for k in range(reps):
+        ev[k][0].record(stream)
+        fn()
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([e[0].elapsed_time(e[1]) for e in ev]))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              "(the path shards by ray ranges with no exchange, see DESIGN.md)", file=sys.stderr)
+              "(the path shards by ray ranges with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -137,17 +162,14 @@ def main():
 
     phase = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(4)] for k in range(args.steps)])
     keys_ms, sort_ms, gather_ms, trace_ms = np.median(phase, axis=0)
+    unsorted_ms = median_ms(torch, stream, unsorted, args.steps)
 
-    uev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
-    for k in range(args.steps):
-        unsorted(uev[k])
-    torch.cuda.synchronize()
-    unsorted_ms = float(np.median([e[0].elapsed_time(e[1]) for e in uev]))
-
-    # correctness of what was timed: the sorted hits scattered back equal the unsorted hits
+    # what was timed is correct: the sorted hits scattered back equal the unsorted hits
     back = rr.rr_scatter_hits(hits, idx)
     torch.cuda.synchronize()
     same = bool(torch.equal(back.view(torch.int32), uhits.view(torch.int32)))
+    prof = rr.rr_trace_profile(scene, srays)
+    uprof = rr.rr_trace_profile(scene, rays)
 
     value = n / (ms_per_step * 1e-3) / 1e6
     trace_bytes = n * (32 + 16)
@@ -167,7 +189,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "bounce2_diffuse_1920x1080_grid_city_1M_tris", "rays": int(n),
                    "triangles": int(w.tris.shape[0]), "key": args.key, "term_ratio": 0.25,
-                   "bvh": ["median", "sah"][args.builder], "step": "keys+sort+gather+trace (sorted hits)"},
+                   "bvh": ["median", "sah"][args.builder] + " collapsed to 4-wide",
+                   "step": "keys+sort+gather+trace, hits in key order"},
         "unsorted_trace_mrays": round(n / (unsorted_ms * 1e-3) / 1e6, 2),
         "trace_speedup_sorted_vs_unsorted": round(unsorted_ms / trace_ms, 3),
         "reorder_vs_unsorted": round(unsorted_ms / ms_per_step, 3),
@@ -175,45 +198,208 @@ def main():
                      "trace_sorted": round(trace_ms, 4), "trace_unsorted": round(unsorted_ms, 4)},
         "sort_gbs": round(sort_bytes / (sort_ms * 1e-3) / 1e9, 1),
         "sort_roofline_frac": round(sort_bytes / (sort_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
+        "simd_efficiency": {"sorted": round(prof["simd_efficiency"], 3),
+                            "unsorted": round(uprof["simd_efficiency"], 3)},
+        "per_ray": {"inner_visits": round(prof["inner_visits"] / n, 2), "leaf_visits": round(prof["leaf_visits"] / n, 2),
+                    "tri_tests": round(prof["tri_tests"] / n, 2)},
         "hits_scatter_back_equal_unsorted": same,
-        "roofline": {"kernel": "k_trace (sorted rays)", "bound": "hbm",
-                     "achieved": round(trace_bytes / (trace_ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(trace_bytes / (trace_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
-                     "traffic": None, "algorithmic_bytes_per_ray": 48},
+        "roofline": trace_roofline(trace_bytes, trace_ms, n),
     }
-    if not args.no_variants:
+    if "variants" not in args.skip:
         result["variants"] = variants(torch, rr, scene, rays, n, lo, hi, dev, stream, args.steps, unsorted_ms)
-    if not args.no_cpu_baseline:
+    if "bounce3" not in args.skip:
+        result["bounce3_2160p"] = bounce3(torch, rr, W, scene, dev, stream, max(5, args.steps // 2))
+    if "batch" not in args.skip:
+        result["batched_64_wavefronts"] = batched(torch, rr, W, scene, w, dev, stream)
+    scene.close()
+    if "serve" not in args.skip:
+        loads = [float(x) for x in args.serve_loads.split(",") if x]
+        result["served"] = served(torch, rr, W, dev, args.serve_requests, loads)
+        main_load = min(result["served"]["loads"], key=lambda r: abs(r["offered_load"] - 0.8))
+        result["p50_ms"] = main_load["p50_ms"]
+        result["p99_ms"] = main_load["p99_ms"]
+    if "cpu" not in args.skip:
         result["cpu_baseline"] = cpu_baseline(w, args.key)
     if args.copy_calibration:
         copy_calibration(torch, dev)
-    scene.close()
     print(json.dumps(result))
 
 
+def trace_roofline(trace_bytes, trace_ms, n):
+    return {"kernel": "k_trace4 (sorted rays)", "bound": "hbm",
+            "achieved": round(trace_bytes / (trace_ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(trace_bytes / (trace_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+            "traffic": None, "algorithmic_bytes_per_ray": 48, "launch_ms": round(trace_ms, 4)}
+
+
 def variants(torch, rr, scene, rays, n, lo, hi, dev, stream, steps, unsorted_ms):
-    """The fused entry point for each key kind (sorted-order hits), and with
-    the hits scattered back to ray order."""
+    """The fused entry point for each key kind: hits in key order, hits
+    scattered back to ray order, and tracing through the sorted index."""
     out = {}
-    for name, (kind, bits) in [("none", (0, 32)), ("od32", (1, 32)), ("od64", (1, 64)), ("ot32", (2, 32)),
-                               ("ot64", (2, 64))]:
+    for name, (kind, bits) in KEYS.items():
         p = rr.key_params(kind, bits, lo, hi, 0.25)
         ws = rr.workspace(rr.reorder_workspace_size(n, p), dev)
         hits = torch.empty((n, 4), dtype=torch.float32, device=dev)
         cnt = torch.empty(1, dtype=torch.int32, device=dev)
         for flags, tag in ((0, ""), (rr.RR_HITS_ORIGINAL_ORDER, "_scatter_back"), (rr.RR_INDIRECT, "_indirect")):
-            for _ in range(2):
+            def run():
                 rr.rr_reorder_and_trace(scene, rays, p, flags=flags, hits=hits, count=cnt, ws=ws, want_perm=False)
-            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
-            for k in range(steps):
-                ev[k][0].record(stream)
-                rr.rr_reorder_and_trace(scene, rays, p, flags=flags, hits=hits, count=cnt, ws=ws, want_perm=False)
-                ev[k][1].record(stream)
-            torch.cuda.synchronize()
-            ms = float(np.median([e[0].elapsed_time(e[1]) for e in ev]))
+            run(); run()
+            ms = median_ms(torch, stream, run, steps)
             out[name + tag] = {"ms": round(ms, 4), "mrays": round(n / (ms * 1e-3) / 1e6, 2),
                                "vs_unsorted": round(unsorted_ms / ms, 3)}
         del ws
+    return out
+
+
+def bounce3(torch, rr, W, scene, dev, stream, steps):
+    """3840x2160 bounce-3 slots on the same city; terminated rays are
+    compacted before the sort.  Rates count live rays."""
+    w3 = W.bounce3_2160p()
+    rays = torch.from_numpy(w3.rays).to(dev)
+    alive = torch.from_numpy(w3.alive).to(dev)
+    n = w3.rays.shape[0]
+    live = int(w3.alive.sum())
+    lo, hi = scene.bounds()
+    out = {"slots": int(n), "live": live}
+    hits = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    for name in ("none", "od32", "od64", "ot64"):
+        kind, bits = KEYS[name]
+        p = rr.key_params(kind, bits, lo, hi, 0.25)
+        ws = rr.workspace(rr.reorder_workspace_size(n, p), dev)
+        for flags, tag in ((0, ""), (rr.RR_HITS_ORIGINAL_ORDER, "_scatter_back")):
+            def run():
+                rr.rr_reorder_and_trace(scene, rays, p, alive=alive, flags=flags, hits=hits, count=cnt, ws=ws,
+                                        want_perm=False)
+            run()
+            ms = median_ms(torch, stream, run, steps)
+            out[name + tag] = {"ms": round(ms, 4), "mrays": round(live / (ms * 1e-3) / 1e6, 2)}
+        assert int(cnt.cpu()[0]) == live
+        del ws
+    return out
+
+
+def batched(torch, rr, W, scene, w, dev, stream):
+    """64 wavefronts, sizes log-uniform in [4K, 2M], each drawn from the
+    primary or bounce 1-4 rays of the 1920x1080 city view, Two Point 64-bit
+    keys, reordered and traced in one graph launch."""
+    c = w.city
+    pools = []
+    r = W.camera_rays(4, 1920, 1080, (c.nx / 2.0, 0.6 * max(c.nx, c.nz), c.nz / 2.0))
+    alive = np.ones(r.shape[0], np.uint8)
+    pools.append(r)
+    for k in range(4):
+        r, alive = W.bounce(c, 4, 200 + k, r, alive)
+        pools.append(np.ascontiguousarray(r[alive.astype(bool)]))
+    sizes = W.segment_sizes(4)
+    lo, hi = scene.bounds()
+    key = rr.key_params(2, 64, lo, hi, 0.25)
+    segs, keep = [], []
+    for i, m in enumerate(sizes):
+        depth = int(W.rngu(4, 41, i) * 5)
+        pool = pools[depth]
+        ix = W.sample_indices(4, 1000 + i, int(m), pool.shape[0])
+        rays = torch.from_numpy(np.ascontiguousarray(pool[ix])).to(dev)
+        hits = torch.empty((int(m), 4), dtype=torch.float32, device=dev)
+        keep.append((rays, hits))
+        segs.append(rr.segment(rays, hits, key))
+    total = int(sizes.sum())
+    out = {"segments": len(segs), "rays": total}
+    with rr.Batch(scene, max_rays=total, max_segments=len(segs)) as b:
+        t0 = time.perf_counter()
+        best, tuned_ms = b.autotune(segs, reps=2)
+        out["autotune_s"] = round(time.perf_counter() - t0, 2)
+        out["config"] = best
+        try:
+            rr.save_tuned(total, 64, best, tuned_ms)
+        except OSError:
+            pass
+        b.run(segs, flags=0)
+        ms = median_ms(torch, stream, lambda: b.run(segs, flags=0), 10)
+        out["graph_ms"] = round(ms, 3)
+        out["mrays"] = round(total / (ms * 1e-3) / 1e6, 2)
+        ms_o = median_ms(torch, stream, lambda: b.run(segs, flags=rr.RR_HITS_ORIGINAL_ORDER), 5)
+        out["graph_scatter_back_ms"] = round(ms_o, 3)
+        # the same wavefronts one call each
+        wss = {}
+        def per_call():
+            for (rays, hits) in keep:
+                m = rays.shape[0]
+                if m not in wss:
+                    wss[m] = rr.workspace(rr.reorder_workspace_size(m, key), dev)
+                rr.rr_reorder_and_trace(scene, rays, key, flags=0, hits=hits, ws=wss[m], want_perm=False)
+        per_call()
+        ms_p = median_ms(torch, stream, per_call, 3)
+        out["per_call_ms"] = round(ms_p, 3)
+        out["per_call_mrays"] = round(total / (ms_p * 1e-3) / 1e6, 2)
+        # unsorted trace of the same rays, one call each
+        def unsorted():
+            for (rays, hits) in keep:
+                rr.rr_trace(scene, rays, hits=hits)
+        ms_u = median_ms(torch, stream, unsorted, 3)
+        out["unsorted_trace_mrays"] = round(total / (ms_u * 1e-3) / 1e6, 2)
+    return out
+
+
+def served(torch, rr, W, dev, n_req, loads):
+    """Poisson streams of requests (ray counts log-uniform in [16K, 4M], key
+    kind drawn per request from none / OD-32 / OD-64 / OT-64, rays drawn
+    from the primary, bounce-1 and bounce-2 rays of a 3840x2160 view) against
+    the grid city scaled 2x2 (~4M triangles), served with continuous
+    batching on 2 streams under a 32 GB workspace budget, at each offered
+    load (a fraction of the measured batched capacity)."""
+    c = W.city(5, 200, 200, 3_520_000)
+    scene = rr.Scene(c.tris)
+    lo, hi = scene.bounds()
+    r = W.camera_rays(5, 3840, 2160, (100.0, 120.0, 100.0))
+    pools = [torch.from_numpy(r).to(dev)]
+    alive = np.ones(r.shape[0], np.uint8)
+    for k in range(2):
+        r, alive = W.bounce(c, 5, 300 + k, r, alive)
+        pools.append(torch.from_numpy(np.ascontiguousarray(r[alive.astype(bool)])).to(dev))
+    kinds = ["none", "od32", "od64", "ot64"]
+    warm = 10
+    reqs = []
+    for i in range(n_req + warm):
+        m = int(math.floor(math.exp(math.log(16384) + W.rngu(5, 50, i) * (math.log(1 << 22) - math.log(16384)))))
+        kname = kinds[int(W.rngu(5, 51, i) * 4)]
+        pool = pools[int(W.rngu(5, 52, i) * 3)]
+        ix = torch.from_numpy(W.sample_indices(5, 2000 + i, m, pool.shape[0])).to(dev)
+        rays = pool.index_select(0, ix).contiguous()
+        hits = torch.empty((m, 4), dtype=torch.float32, device=dev)
+        kind, bits = KEYS[kname]
+        reqs.append((rays, hits, rr.key_params(kind, bits, lo, hi, 0.25), kname))
+    # batched capacity on this scene, to set the arrival rates
+    segs = [rr.segment(a, b, k) for a, b, k, _ in reqs[warm:warm + 8]]
+    stream = torch.cuda.current_stream()
+    with rr.Batch(scene, max_rays=sum(int(s.n) for s in segs), max_segments=8) as b:
+        b.run(segs)
+        ms = median_ms(torch, stream, lambda: b.run(segs), 3)
+    cap_rays_s = sum(int(s.n) for s in segs) / (ms * 1e-3)
+    mean_n = float(np.mean([x[0].shape[0] for x in reqs[warm:]]))
+    out = {"scene_triangles": int(c.tris.shape[0]), "requests": n_req, "slots": 2,
+           "capacity_mrays": round(cap_rays_s / 1e6, 1), "mean_request_rays": int(mean_n), "loads": []}
+    cfg = dict(slots=2, hbm_budget_bytes=32 << 30, max_batch_rays=1 << 23, max_batch_requests=16)
+    with rr.Server(scene, **cfg) as sv:
+        sv.start()
+        for rays, hits, key, _ in reqs[:warm]:
+            sv.submit(rays, hits, key)
+        sv.drain(300.0)
+    for li, load in enumerate(loads):
+        lam = load * cap_rays_s / mean_n
+        with rr.Server(scene, **cfg) as sv:
+            t = 0.02
+            for i, (rays, hits, key, _) in enumerate(reqs[warm:]):
+                sv.submit(rays, hits, key, arrival_s=t)
+                t += -math.log(1.0 - W.rngu(5, 60 + li, i)) / lam
+            sv.start()
+            sv.drain(600.0)
+            st = sv.stats()
+        row = {"offered_load": load, "arrival_rate_per_s": round(lam, 1)}
+        row.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()})
+        out["loads"].append(row)
+    scene.close()
     return out
 
 
