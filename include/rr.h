@@ -113,8 +113,11 @@ rr_status rr_device_count(int32_t* count);
  * device memory until rr_scene_destroy; it is immutable and may be shared
  * by concurrent calls on any stream of that device.
  *  builder (rr_scene_create_ex): 0 = median split (balanced), 1 = binned
- *  surface area heuristic (what rr_scene_create uses).  Results of rr_trace
- *  do not depend on the builder. */
+ *  surface area heuristic (what rr_scene_create uses); or'ed with
+ *  RR_BUILD_FULL_NODES, the 4-wide nodes keep full binary32 child bounds
+ *  (128 bytes) instead of 8-bit bounds quantised outward against the parent
+ *  box (64 bytes).  Results of rr_trace do not depend on either choice. */
+#define RR_BUILD_FULL_NODES 2
 rr_status rr_scene_create(const float* tri_xyz_host, int64_t n_tris, rr_scene* out);
 rr_status rr_scene_create_ex(const float* tri_xyz_host, int64_t n_tris, int32_t builder, rr_scene* out);
 rr_status rr_scene_bounds(rr_scene s, float lo[3], float hi[3]);

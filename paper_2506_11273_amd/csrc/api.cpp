@@ -88,7 +88,7 @@ rr_status rr_scene_create_ex(const float* tri, int64_t n_tris, int32_t builder, 
   if (!out) return RR_ERR_INVALID_ARGUMENT;
   *out = nullptr;
   if (!tri || n_tris <= 0 || n_tris >= (int64_t(1) << 28)) return RR_ERR_INVALID_ARGUMENT;
-  if (builder != 0 && builder != 1) return RR_ERR_INVALID_ARGUMENT;
+  if ((builder & ~(1 | RR_BUILD_FULL_NODES)) != 0) return RR_ERR_INVALID_ARGUMENT;
   for (int64_t i = 0; i < 9 * n_tris; ++i)
     if (!std::isfinite(tri[i])) return RR_ERR_INVALID_ARGUMENT;
   rr_scene s = new (std::nothrow) rr_scene_s;

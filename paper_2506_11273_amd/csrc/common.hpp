@@ -77,6 +77,7 @@ struct DeviceScene {
   int64_t n_tris = 0;
   int32_t depth = 0;
   int32_t device = 0;
+  int32_t quantised = 1;     // 64-byte nodes with 8-bit child bounds, else 128-byte nodes
   float lo[3], hi[3];
   size_t bytes = 0;
 };

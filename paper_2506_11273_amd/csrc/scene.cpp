@@ -173,12 +173,69 @@ struct Builder {
 // Emits the 4-wide BVH: each binary inner node is widened by repeatedly
 // replacing its largest-area inner child with that child's two children
 // until it has four children or only leaves remain.
+// 8-bit quantised child bounds (compressed 64-byte node): per axis an
+// origin p (the node's lower bound) and a power-of-two step s with
+// 255 * s >= extent; a child bound is stored as q with decoded value
+// fl(p + q * s) (q * s is exact).  q is rounded outward and then checked with
+// that same binary32 arithmetic, so the decoded box always contains the
+// child's exact box.
+void quantize_node(const Box* kids, int m, const int32_t* code, float4* out) {
+  Box P;
+  for (int j = 0; j < m; ++j) P.grow(kids[j]);
+  float p[3], s[3];
+  uint32_t ebits = 0;
+  for (int a = 0; a < 3; ++a) {
+    p[a] = P.lo[a];
+    const double ext = (double)P.hi[a] - (double)P.lo[a];
+    int e = -100;
+    if (ext > 0) {
+      e = (int)std::ceil(std::log2(ext / 255.0));
+      while (std::ldexp(255.0, e) < ext) ++e;
+      while (e > -100 && std::ldexp(255.0, e - 1) >= ext) --e;
+    }
+    e = std::max(-100, std::min(100, e));
+    s[a] = std::ldexp(1.0f, e);
+    ebits |= (uint32_t)(e + 127) << (8 * a);
+  }
+  auto dec = [&](int a, uint32_t q) {
+    const float qs = (float)q * s[a];
+    return p[a] + qs;
+  };
+  uint32_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int j = 0; j < m; ++j)
+    for (int a = 0; a < 3; ++a) {
+      double ql = std::floor(((double)kids[j].lo[a] - (double)p[a]) / (double)s[a]);
+      double qh = std::ceil(((double)kids[j].hi[a] - (double)p[a]) / (double)s[a]);
+      uint32_t l = (uint32_t)std::max(0.0, std::min(255.0, ql));
+      uint32_t h = (uint32_t)std::max(0.0, std::min(255.0, qh));
+      while (l > 0 && dec(a, l) > kids[j].lo[a]) --l;
+      while (h < 255 && dec(a, h) < kids[j].hi[a]) ++h;
+      lo[a] |= l << (8 * j);
+      hi[a] |= h << (8 * j);
+    }
+  auto f = [](uint32_t v) {
+    float x;
+    std::memcpy(&x, &v, 4);
+    return x;
+  };
+  auto fi = [](int32_t v) {
+    float x;
+    std::memcpy(&x, &v, 4);
+    return x;
+  };
+  out[0] = make_float4(p[0], p[1], p[2], f(ebits));
+  out[1] = make_float4(f(lo[0]), f(hi[0]), f(lo[1]), f(hi[1]));
+  out[2] = make_float4(f(lo[2]), f(hi[2]), 0.0f, 0.0f);
+  out[3] = make_float4(fi(code[0]), fi(code[1]), fi(code[2]), fi(code[3]));
+}
+
 struct Packer {
   const float* tris;
   const std::vector<int32_t>& order;
   std::vector<float4> nodes;
   std::vector<float4> gtris;
   int max_depth = 0;
+  int stride = 8;  // float4 per node: 8 full-precision, 4 quantised
 
   int32_t leaf(const BNode* n) {
     const int32_t first = (int32_t)(gtris.size() / 3);
@@ -214,10 +271,16 @@ struct Packer {
       kids[best] = x->kid[0].get();
       kids[m++] = x->kid[1].get();
     }
-    const int32_t me = (int32_t)(nodes.size() / 8);
-    nodes.resize(nodes.size() + 8);
+    const int32_t me = (int32_t)(nodes.size() / stride);
+    nodes.resize(nodes.size() + stride);
     int32_t code[4] = {kEmptyChild, kEmptyChild, kEmptyChild, kEmptyChild};
     for (int j = 0; j < m; ++j) code[j] = pack(kids[j], depth + 1);
+    if (stride == 4) {
+      Box kb[4];
+      for (int j = 0; j < m; ++j) kb[j] = kids[j]->box;
+      quantize_node(kb, m, code, nodes.data() + 4 * (size_t)me);
+      return me;
+    }
     float lo[3][4], hi[3][4];
     for (int j = 0; j < 4; ++j)
       for (int k = 0; k < 3; ++k) {
@@ -240,6 +303,8 @@ struct Packer {
 }  // namespace
 
 rr_status build_scene(const float* tris, int64_t n, int builder, DeviceScene* out) {
+  const bool quantised = (builder & RR_BUILD_FULL_NODES) == 0;
+  builder &= 1;
   std::vector<Prim> prims((size_t)n);
   Box scene;
   for (int64_t i = 0; i < n; ++i) {
@@ -253,15 +318,16 @@ rr_status build_scene(const float* tris, int64_t n, int builder, DeviceScene* ou
   for (int64_t i = 0; i < n; ++i) order[(size_t)i] = (int32_t)i;
   Builder B(prims, order, builder);
   std::unique_ptr<BNode> root = B.build(0, n, 0);
-  Packer P{tris, order, {}, {}, 0};
-  P.nodes.reserve((size_t)(n / 4 + 8) * 8);
+  Packer P{tris, order, {}, {}, 0, quantised ? 4 : 8};
+  P.nodes.reserve((size_t)(n / 4 + 8) * P.stride);
   P.gtris.reserve((size_t)n * 3);
   const int32_t root_code = P.pack(root.get(), 0);
   if (P.max_depth > kMaxTreeDepth) return RR_ERR_UNSUPPORTED;
 
   DeviceScene d;
   d.root = root_code;
-  d.n_nodes = (int64_t)(P.nodes.size() / 8);
+  d.n_nodes = (int64_t)(P.nodes.size() / P.stride);
+  d.quantised = quantised ? 1 : 0;
   d.n_tris = n;
   d.depth = P.max_depth;
   for (int k = 0; k < 3; ++k) {
@@ -269,7 +335,7 @@ rr_status build_scene(const float* tris, int64_t n, int builder, DeviceScene* ou
     d.hi[k] = scene.hi[k];
   }
   if (hipGetDevice(&d.device) != hipSuccess) return RR_ERR_DEVICE;
-  const size_t nb = std::max<size_t>(P.nodes.size(), 8) * sizeof(float4);
+  const size_t nb = std::max<size_t>(P.nodes.size(), 8) * sizeof(float4);  // at least one node of either kind
   const size_t tb = P.gtris.size() * sizeof(float4);
   if (hipMalloc(&d.nodes, nb) != hipSuccess) return RR_ERR_OUT_OF_MEMORY;
   if (hipMalloc(&d.tris, tb) != hipSuccess) {

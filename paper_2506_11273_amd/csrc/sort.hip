@@ -31,6 +31,8 @@ namespace {
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / kWave;
 constexpr uint32_t kSpinLimit = 1u << 18;
+constexpr int kLookback = 16;  // predecessors read per look-back round trip
+constexpr uint32_t kHistUnit = 4096;  // keys per histogram work unit (16 per thread)
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -90,9 +92,10 @@ __global__ void k_seg_init(const SortHdr* hdr, uint32_t* __restrict__ hist, uint
     for (uint32_t i = threadIdx.x; i < n_counters; i += blockDim.x) counters[i] = 0;
 }
 
-// Digit histograms of every pass per segment (blocks take contiguous runs
-// of tiles, flushing their LDS counts when the segment changes), plus
-// clearing of the look-back words the passes will use.
+// Digit histograms of every pass per segment.  Blocks take contiguous runs
+// of kHistUnit-key units (a unit never straddles a segment), load a unit's
+// keys before counting them, and flush their LDS counts when the segment
+// changes; the look-back words the passes will use are cleared too.
 template <typename K, int DB, int KPT>
 __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__ keys, const SortHdr* hdr,
                                                            const SortSeg* __restrict__ segs, uint32_t passes,
@@ -101,16 +104,22 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
                                                            uint32_t status_pass_stride) {
   constexpr uint32_t R = 1u << DB;
   constexpr uint32_t kTile = kSortThreads * KPT;
+  constexpr uint32_t kUnitsPerTile = kTile >= kHistUnit ? kTile / kHistUnit : 1u;
+  constexpr uint32_t kUnitKeys = kTile >= kHistUnit ? kHistUnit : kTile;
+  constexpr uint32_t kPer = kUnitKeys / kSortThreads;
   constexpr uint32_t kMaxPasses = (8 * sizeof(K) + DB - 1) / DB;
+  static_assert(kHistUnit % kSortThreads == 0, "unit size");
   __shared__ uint32_t s_h[kMaxPasses * R];
   const uint32_t nseg = hdr->nseg, T = hdr->total_tiles;
+  const uint32_t U = T * kUnitsPerTile;
   const uint32_t words = passes * R;
   for (uint32_t i = threadIdx.x; i < words; i += kSortThreads) s_h[i] = 0;
   __syncthreads();
-  const uint32_t t0 = (uint32_t)(((uint64_t)blockIdx.x * T) / gridDim.x);
-  const uint32_t t1 = (uint32_t)(((uint64_t)(blockIdx.x + 1) * T) / gridDim.x);
-  uint32_t cur = t0 < t1 ? seg_of_tile(segs, nseg, t0) : 0u;
-  for (uint32_t t = t0; t < t1; ++t) {
+  const uint32_t u0 = (uint32_t)(((uint64_t)blockIdx.x * U) / gridDim.x);
+  const uint32_t u1 = (uint32_t)(((uint64_t)(blockIdx.x + 1) * U) / gridDim.x);
+  uint32_t cur = u0 < u1 ? seg_of_tile(segs, nseg, u0 / kUnitsPerTile) : 0u;
+  for (uint32_t u = u0; u < u1; ++u) {
+    const uint32_t t = u / kUnitsPerTile;
     uint32_t s = cur;
     while (s + 1 < nseg && segs[s + 1].tile_off <= t) ++s;  // block-uniform
     if (s != cur) {
@@ -123,15 +132,23 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
       cur = s;
     }
     const SortSeg sg = segs[s];
-    const uint32_t first = sg.off + (t - sg.tile_off) * kTile;
-    const uint32_t last = min(first + kTile, sg.off + sg.n);
-    for (uint32_t i = first + threadIdx.x; i < last; i += kSortThreads) {
-      const K k = keys[i];
-      for (uint32_t p = 0; p < passes; ++p) atomicAdd(&s_h[p * R + ((uint32_t)(k >> (p * DB)) & (R - 1))], 1u);
+    const uint32_t first = sg.off + (t - sg.tile_off) * kTile + (u % kUnitsPerTile) * kUnitKeys;
+    const uint32_t last = sg.off + sg.n;
+    K k[kPer];
+#pragma unroll
+    for (uint32_t q = 0; q < kPer; ++q) {
+      const uint32_t i = first + q * kSortThreads + threadIdx.x;
+      k[q] = i < last ? keys[i] : (K)0;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < kPer; ++q) {
+      if (first + q * kSortThreads + threadIdx.x >= last) continue;
+      for (uint32_t p = 0; p < passes; ++p)
+        atomicAdd(&s_h[p * R + ((uint32_t)(k[q] >> (p * DB)) & (R - 1))], 1u);
     }
   }
   __syncthreads();
-  if (t0 < t1)
+  if (u0 < u1)
     for (uint32_t i = threadIdx.x; i < words; i += kSortThreads)
       if (s_h[i]) atomicAdd(&hist[(size_t)cur * words + i], s_h[i]);
   // clear the look-back words of the tiles this sort will use
@@ -255,28 +272,48 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
     const uint32_t local = block_scan_256(tid < R ? count : 0u, sm.scan, &total);
     if (tid < R) sm.local_off[tid] = local;
 
-    // ---- decoupled look-back over this segment's earlier tiles
+    // ---- decoupled look-back over this segment's earlier tiles, reading a
+    // window of kLookback predecessors per round trip: aggregates are summed
+    // up to the nearest published prefix; an unpublished entry is waited on.
     if (tid < R) {
       const uint32_t d = tid;
       uint32_t prefix = 0;
       if (tile_in > 0) {
-        int64_t j = (int64_t)tile - 1;
+        int64_t j = (int64_t)tile - 1;  // nearest tile not yet accounted for
         uint32_t spins = 0;
         while (j >= (int64_t)sg.tile_off) {
-          const uint32_t w =
-              __hip_atomic_load(&status[(size_t)j * R + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const uint32_t flag = w & ~kStatusCountMask;
-          if (flag == 0) {
+          uint32_t w[kLookback];
+#pragma unroll
+          for (int q = 0; q < kLookback; ++q)
+            w[q] = (j - q >= (int64_t)sg.tile_off)
+                       ? __hip_atomic_load(&status[(size_t)(j - q) * R + d], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT)
+                       : kStatusPrefix;  // below the segment: acts as a zero prefix
+          uint32_t acc = 0;
+          int used = 0;
+          bool found = false, blocked = false;
+#pragma unroll
+          for (int q = 0; q < kLookback; ++q) {
+            if (found || blocked) continue;
+            const uint32_t flag = w[q] & ~kStatusCountMask;
+            if (flag == 0) {
+              blocked = true;
+            } else {
+              acc += w[q] & kStatusCountMask;
+              ++used;
+              if (flag == kStatusPrefix) found = true;
+            }
+          }
+          prefix += acc;
+          if (found) break;
+          j -= used;
+          if (blocked) {
             if (++spins > kSpinLimit) {
               atomicOr(err, 1u);
               break;
             }
             __builtin_amdgcn_s_sleep(1);
-            continue;
           }
-          prefix += w & kStatusCountMask;
-          if (flag == kStatusPrefix) break;
-          --j;
         }
         __hip_atomic_store(&status[(size_t)tile * R + d], kStatusPrefix | (prefix + count), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -357,7 +394,10 @@ rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, So
     hipLaunchKernelGGL(k_seg_setup_single, dim3(1), dim3(64), 0, st, count_dev, n_max, L.tile, hdr, segs);
   hipLaunchKernelGGL(k_seg_init, dim3(std::max(1u, std::min(64u, L.max_seg))), dim3(256), 0, st, hdr, hist,
                      L.passes * R, counters, L.passes + 1);
-  const uint32_t hist_blocks = std::max(1u, std::min(max_tiles, std::min(hist_res, 2048u)));
+  // about one unit per block: each block flushes its whole histogram with
+  // global atomics, so more blocks than units only adds flush traffic
+  const uint32_t hist_units = std::max(1u, max_tiles * L.tile / kHistUnit);
+  const uint32_t hist_blocks = std::max(1u, std::min(hist_units, std::min(hist_res, 1024u)));
   hipLaunchKernelGGL((k_seg_hist<K, DB, KPT>), dim3(hist_blocks), dim3(kSortThreads), 0, st, keys, hdr, segs,
                      L.passes, hist, status, L.status_stride);
   hipLaunchKernelGGL((k_seg_scan<DB>), dim3(L.max_seg * L.passes), dim3(kSortThreads), 0, st, hdr, segs, L.passes,

@@ -12,10 +12,14 @@
 // defining minimum and the result does not depend on ray order, BVH or
 // launch shape.
 //
-// Layout: an inner node is 8 x float4 = 128 bytes, its four child boxes in
-// SoA form: lo.x[4], hi.x[4], lo.y[4], hi.y[4], lo.z[4], hi.z[4], child[4],
-// unused.  A child >= 0 is an inner node, kEmptyChild an unused slot, and a
-// child < 0 a leaf ~(first << 3 | count) of at most 4 triangles.
+// Layout: a 4-wide inner node is either 8 x float4 = 128 bytes holding its
+// four child boxes in SoA form (lo.x[4], hi.x[4], lo.y[4], hi.y[4], lo.z[4],
+// hi.z[4], child[4], unused), or 4 x float4 = 64 bytes with the child bounds
+// quantised to 8 bits against the node box: (p.xyz, step exponents),
+// (lo.x, hi.x, lo.y, hi.y as 4 bytes each), (lo.z, hi.z, -, -), child[4];
+// a bound decodes to p + q * 2^e, rounded outward by the builder.  A child
+// >= 0 is an inner node, kEmptyChild an unused slot, and a child < 0 a leaf
+// ~(first << 3 | count) of at most 4 triangles.
 // A triangle is 3 x float4 = 48 bytes: (v0, e1.x), (e1.yz, e2.xy),
 // (e2.z, prim id bits, -, -), with e1 = v1 - v0 and e2 = v2 - v0.
 //
@@ -77,6 +81,13 @@ __device__ __forceinline__ bool slab(float lx, float hx, float ly, float hy, flo
   return n <= f;
 }
 
+// Decoded bound of a quantised node: fl(p + q * s), q * s exact (the
+// scene builder checks its quantisation with this same arithmetic).
+__device__ __forceinline__ float dq(float p, uint32_t word, int j, float s) {
+  const float qs = (float)((word >> (8 * j)) & 0xFFu) * s;
+  return p + qs;
+}
+
 __device__ __forceinline__ void cswap(float& ta, int32_t& ca, float& tb, int32_t& cb) {
   const bool s = tb < ta;
   const float t = s ? tb : ta;
@@ -87,7 +98,7 @@ __device__ __forceinline__ void cswap(float& ta, int32_t& ca, float& tb, int32_t
   ca = c;
 }
 
-template <int BLOCK, bool STATS>
+template <int BLOCK, bool STATS, bool QNODE>
 __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                                   int32_t root, const float4* __restrict__ rays,
                                                   const uint32_t* __restrict__ idx, const uint32_t* count_dev,
@@ -160,14 +171,37 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
     bool pop = true;
     if (node >= 0 && node != kEmptyChild) {
       if (STATS) ++st_inner;
-      const float4* N = nodes + 8 * (size_t)node;
-      const float4 lx = N[0], hx = N[1], ly = N[2], hy = N[3], lz = N[4], hz = N[5];
-      const int4 cc = *reinterpret_cast<const int4*>(N + 6);
       float t0, t1, t2, t3;
-      const bool h0 = slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, R, tbest, &t0) && cc.x != kEmptyChild;
-      const bool h1 = slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, R, tbest, &t1) && cc.y != kEmptyChild;
-      const bool h2 = slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, R, tbest, &t2) && cc.z != kEmptyChild;
-      const bool h3 = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, R, tbest, &t3) && cc.w != kEmptyChild;
+      bool h0, h1, h2, h3;
+      int4 cc;
+      if constexpr (QNODE) {
+        const float4* N = nodes + 4 * (size_t)node;
+        const float4 a = N[0], b = N[1], c = N[2];
+        cc = *reinterpret_cast<const int4*>(N + 3);
+        const uint32_t eb = __float_as_uint(a.w);
+        const float sx = __uint_as_float((eb & 0xFFu) << 23);
+        const float sy = __uint_as_float(((eb >> 8) & 0xFFu) << 23);
+        const float sz = __uint_as_float(((eb >> 16) & 0xFFu) << 23);
+        const uint32_t qlx = __float_as_uint(b.x), qhx = __float_as_uint(b.y);
+        const uint32_t qly = __float_as_uint(b.z), qhy = __float_as_uint(b.w);
+        const uint32_t qlz = __float_as_uint(c.x), qhz = __float_as_uint(c.y);
+        h0 = slab(dq(a.x, qlx, 0, sx), dq(a.x, qhx, 0, sx), dq(a.y, qly, 0, sy), dq(a.y, qhy, 0, sy),
+                  dq(a.z, qlz, 0, sz), dq(a.z, qhz, 0, sz), R, tbest, &t0) && cc.x != kEmptyChild;
+        h1 = slab(dq(a.x, qlx, 1, sx), dq(a.x, qhx, 1, sx), dq(a.y, qly, 1, sy), dq(a.y, qhy, 1, sy),
+                  dq(a.z, qlz, 1, sz), dq(a.z, qhz, 1, sz), R, tbest, &t1) && cc.y != kEmptyChild;
+        h2 = slab(dq(a.x, qlx, 2, sx), dq(a.x, qhx, 2, sx), dq(a.y, qly, 2, sy), dq(a.y, qhy, 2, sy),
+                  dq(a.z, qlz, 2, sz), dq(a.z, qhz, 2, sz), R, tbest, &t2) && cc.z != kEmptyChild;
+        h3 = slab(dq(a.x, qlx, 3, sx), dq(a.x, qhx, 3, sx), dq(a.y, qly, 3, sy), dq(a.y, qhy, 3, sy),
+                  dq(a.z, qlz, 3, sz), dq(a.z, qhz, 3, sz), R, tbest, &t3) && cc.w != kEmptyChild;
+      } else {
+        const float4* N = nodes + 8 * (size_t)node;
+        const float4 lx = N[0], hx = N[1], ly = N[2], hy = N[3], lz = N[4], hz = N[5];
+        cc = *reinterpret_cast<const int4*>(N + 6);
+        h0 = slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, R, tbest, &t0) && cc.x != kEmptyChild;
+        h1 = slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, R, tbest, &t1) && cc.y != kEmptyChild;
+        h2 = slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, R, tbest, &t2) && cc.z != kEmptyChild;
+        h3 = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, R, tbest, &t3) && cc.w != kEmptyChild;
+      }
       const int m = (int)h0 + (int)h1 + (int)h2 + (int)h3;
       if (m > 0) {
         const float inf = __int_as_float(0x7f800000);
@@ -250,37 +284,44 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
 
 constexpr int kTraceBlock = 256;
 
-template <bool STATS>
+template <bool STATS, bool QNODE>
 uint32_t resident_blocks() {
-  static uint32_t cached[2] = {0, 0};
-  if (cached[STATS]) return cached[STATS];
+  static uint32_t cached = 0;
+  if (cached) return cached;
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
     cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace4<kTraceBlock, STATS>, kTraceBlock, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace4<kTraceBlock, STATS, QNODE>, kTraceBlock, 0) !=
           hipSuccess ||
       per <= 0)
     per = 4;
-  cached[STATS] = (uint32_t)(cus * per);
-  return cached[STATS];
+  cached = (uint32_t)(cus * per);
+  return cached;
+}
+
+template <bool STATS, bool QNODE>
+rr_status launch4q(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
+                   const uint32_t* count_dev, rr_hit* hits, uint32_t refill, TraceStats* stats, hipStream_t st) {
+  // enough waves to fill the device, but at least one full wave of rays each
+  const uint64_t waves_needed = (uint64_t)(n_max + kWave - 1) / kWave;
+  const uint64_t blocks_needed = (waves_needed + kTraceBlock / kWave - 1) / (kTraceBlock / kWave);
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>(blocks_needed, resident_blocks<STATS, QNODE>());
+  hipLaunchKernelGGL((k_trace4<kTraceBlock, STATS, QNODE>), dim3(blocks), dim3(kTraceBlock), 0, st, s.nodes,
+                     s.tris, s.root, reinterpret_cast<const float4*>(rays), idx, count_dev, (uint32_t)n_max,
+                     reinterpret_cast<float4*>(hits), refill, stats);
+  RR_LAUNCH_CHECK();
+  return RR_OK;
 }
 
 template <bool STATS>
 rr_status launch4(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
                   const uint32_t* count_dev, rr_hit* hits, uint32_t refill, TraceStats* stats, hipStream_t st) {
   if (n_max <= 0) return RR_OK;
-  // enough waves to fill the device, but at least one full wave of rays each
-  const uint64_t waves_needed = (uint64_t)(n_max + kWave - 1) / kWave;
-  const uint64_t blocks_needed = (waves_needed + kTraceBlock / kWave - 1) / (kTraceBlock / kWave);
-  const uint32_t blocks = (uint32_t)std::min<uint64_t>(blocks_needed, resident_blocks<STATS>());
   if (refill < 1) refill = 1;
   if (refill > (uint32_t)kWave) refill = kWave;
-  hipLaunchKernelGGL((k_trace4<kTraceBlock, STATS>), dim3(blocks), dim3(kTraceBlock), 0, st, s.nodes, s.tris,
-                     s.root, reinterpret_cast<const float4*>(rays), idx, count_dev, (uint32_t)n_max,
-                     reinterpret_cast<float4*>(hits), refill, stats);
-  RR_LAUNCH_CHECK();
-  return RR_OK;
+  return s.quantised ? launch4q<STATS, true>(s, rays, idx, n_max, count_dev, hits, refill, stats, st)
+                     : launch4q<STATS, false>(s, rays, idx, n_max, count_dev, hits, refill, stats, st);
 }
 
 }  // namespace
@@ -296,8 +337,10 @@ rr_status launch_trace_refill(const DeviceScene& s, const rr_ray* rays, const ui
 }
 
 void trace_warm() {
-  (void)resident_blocks<false>();
-  (void)resident_blocks<true>();
+  (void)resident_blocks<false, false>();
+  (void)resident_blocks<false, true>();
+  (void)resident_blocks<true, false>();
+  (void)resident_blocks<true, true>();
 }
 
 rr_status launch_trace_stats(const DeviceScene& s, const rr_ray* rays, int64_t n_max, rr_hit* hits,
