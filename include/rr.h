@@ -107,9 +107,10 @@ const char* rr_status_string(rr_status s);
 rr_status rr_device_count(int32_t* count);
 
 /* ------------------------------------------------------------------ scene
- * Builds a binary BVH over n_tris triangles and uploads it to the current
+ * Builds a BVH over n_tris triangles and uploads it to the current
  * device.  tri_xyz_host is a HOST array of n_tris x 9 floats
- * {v0.xyz, v1.xyz, v2.xyz}, read during the call only.  The scene owns its
+ * {v0.xyz, v1.xyz, v2.xyz}, read during the call only; coordinates must be
+ * finite and below 1e18 in magnitude (RR_ERR_INVALID_ARGUMENT otherwise).  The scene owns its
  * device memory until rr_scene_destroy; it is immutable and may be shared
  * by concurrent calls on any stream of that device.
  *  builder (rr_scene_create_ex): 0 = median split (balanced), 1 = binned

@@ -89,8 +89,9 @@ rr_status rr_scene_create_ex(const float* tri, int64_t n_tris, int32_t builder, 
   *out = nullptr;
   if (!tri || n_tris <= 0 || n_tris >= (int64_t(1) << 28)) return RR_ERR_INVALID_ARGUMENT;
   if ((builder & ~(1 | RR_BUILD_FULL_NODES)) != 0) return RR_ERR_INVALID_ARGUMENT;
+  // finite coordinates below 1e18 in magnitude keep every traversal term finite
   for (int64_t i = 0; i < 9 * n_tris; ++i)
-    if (!std::isfinite(tri[i])) return RR_ERR_INVALID_ARGUMENT;
+    if (!(std::fabs(tri[i]) < 1e18f)) return RR_ERR_INVALID_ARGUMENT;
   rr_scene s = new (std::nothrow) rr_scene_s;
   if (!s) return RR_ERR_OUT_OF_MEMORY;
   rr_status st;

@@ -184,6 +184,12 @@ void quantize_node(const Box* kids, int m, const int32_t* code, float4* out) {
   for (int j = 0; j < m; ++j) P.grow(kids[j]);
   float p[3], s[3];
   uint32_t ebits = 0;
+  // The trace kernel places plane q at the exact real p + q * 2^e (it never
+  // rounds that sum), so the checks below bound the exact sum: D = p + q * s
+  // in double is within 2^-53 |D| of it, and a margin of 2^-52 |D| makes
+  // each comparison hold for the exact value.
+  auto below = [](double D, float x) { return D + std::fabs(D) * 0x1p-52 <= (double)x; };
+  auto above = [](double D, float x) { return D - std::fabs(D) * 0x1p-52 >= (double)x; };
   for (int a = 0; a < 3; ++a) {
     p[a] = P.lo[a];
     const double ext = (double)P.hi[a] - (double)P.lo[a];
@@ -193,14 +199,12 @@ void quantize_node(const Box* kids, int m, const int32_t* code, float4* out) {
       while (std::ldexp(255.0, e) < ext) ++e;
       while (e > -100 && std::ldexp(255.0, e - 1) >= ext) --e;
     }
-    e = std::max(-100, std::min(100, e));
+    e = std::max(-100, e);
+    while (!above((double)p[a] + std::ldexp(255.0, e), P.hi[a])) ++e;
     s[a] = std::ldexp(1.0f, e);
     ebits |= (uint32_t)(e + 127) << (8 * a);
   }
-  auto dec = [&](int a, uint32_t q) {
-    const float qs = (float)q * s[a];
-    return p[a] + qs;
-  };
+  auto dec = [&](int a, uint32_t q) { return (double)p[a] + (double)q * (double)s[a]; };
   uint32_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   for (int j = 0; j < m; ++j)
     for (int a = 0; a < 3; ++a) {
@@ -208,8 +212,8 @@ void quantize_node(const Box* kids, int m, const int32_t* code, float4* out) {
       double qh = std::ceil(((double)kids[j].hi[a] - (double)p[a]) / (double)s[a]);
       uint32_t l = (uint32_t)std::max(0.0, std::min(255.0, ql));
       uint32_t h = (uint32_t)std::max(0.0, std::min(255.0, qh));
-      while (l > 0 && dec(a, l) > kids[j].lo[a]) --l;
-      while (h < 255 && dec(a, h) < kids[j].hi[a]) ++h;
+      while (l > 0 && !below(dec(a, l), kids[j].lo[a])) --l;
+      while (h < 255 && !above(dec(a, h), kids[j].hi[a])) ++h;
       lo[a] |= l << (8 * j);
       hi[a] |= h << (8 * j);
     }

@@ -17,7 +17,8 @@
 // hi.z[4], child[4], unused), or 4 x float4 = 64 bytes with the child bounds
 // quantised to 8 bits against the node box: (p.xyz, step exponents),
 // (lo.x, hi.x, lo.y, hi.y as 4 bytes each), (lo.z, hi.z, -, -), child[4];
-// a bound decodes to p + q * 2^e, rounded outward by the builder.  A child
+// a bound decodes to the exact p + q * 2^e, codes chosen by the builder so
+// that these planes enclose the child box.  A child
 // >= 0 is an inner node, kEmptyChild an unused slot, and a child < 0 a leaf
 // ~(first << 3 | count) of at most 4 triangles.
 // A triangle is 3 x float4 = 48 bytes: (v0, e1.x), (e1.yz, e2.xy),
@@ -81,11 +82,36 @@ __device__ __forceinline__ bool slab(float lx, float hx, float ly, float hy, flo
   return n <= f;
 }
 
-// Decoded bound of a quantised node: fl(p + q * s), q * s exact (the
-// scene builder checks its quantisation with this same arithmetic).
-__device__ __forceinline__ float dq(float p, uint32_t word, int j, float s) {
-  const float qs = (float)((word >> (8 * j)) & 0xFFu) * s;
-  return p + qs;
+// Ray distances to the lower and upper planes of the four children of a
+// quantised node along one axis, in ray-relative form: with delta = p - o,
+// a plane q lies at t = q * (s * inv) + delta * inv, one fused multiply-add
+// per plane.  The rounding of delta, of s * inv and of the products is
+// bounded by (|delta| + 256 s) * |inv| * 2^-22, so every plane is first
+// moved outward by eps = (|delta| + 256 s) * 2^-20: the computed slab then
+// contains the slab of the decoded box, which contains the child's box.
+// (Coordinates are below 1e18 and steps below 2^61, so nothing overflows.)
+__device__ __forceinline__ void qaxis(float p, float s, float o, float inv, uint32_t wlo, uint32_t whi,
+                                      float (&tlo)[4], float (&thi)[4]) {
+  const float delta = p - o;
+  const float eps = (fabsf(delta) + 256.0f * s) * 0x1p-20f;
+  const float step = s * inv;
+  const float blo = (delta - eps) * inv;
+  const float bhi = (delta + eps) * inv;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    tlo[j] = __builtin_fmaf((float)((wlo >> (8 * j)) & 0xFFu), step, blo);
+    thi[j] = __builtin_fmaf((float)((whi >> (8 * j)) & 0xFFu), step, bhi);
+  }
+}
+
+// Slab test from precomputed plane distances (see qaxis).
+__device__ __forceinline__ bool qslab(float ax, float bx, float ay, float by, float az, float bz, float tmin,
+                                      float tbest, float* tn) {
+  const float n = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), tmin));
+  float f = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tbest));
+  f = __builtin_fmaf(fabsf(f), kFarSlack, f);
+  *tn = n;
+  return n <= f;
 }
 
 __device__ __forceinline__ void cswap(float& ta, int32_t& ca, float& tb, int32_t& cb) {
@@ -123,7 +149,8 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
 
   Ray R{};
   int32_t slot = -1;  // ray slot this lane works on, -1 when idle
-  int32_t node = 0;
+  int32_t node = 0;   // next node to visit: inner node, leaf code, or kEmptyChild when none is left
+  int32_t leaf = 0;   // postponed leaf code, 0 when none
   int sp = 0;
   float tbest = 0.0f, bu = 0.0f, bv = 0.0f;
   int32_t bprim = -1;
@@ -158,41 +185,53 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
           bprim = -1;
           bu = bv = 0.0f;
           sp = 0;
+          leaf = 0;
           if (STATS) ++st_rays;
         }
       }
       next = next + n_idle < end ? next + n_idle : end;
     }
-    if (STATS) st_wave += kWave;
+    // counts one wave iteration per wave (by the lowest active lane)
+    auto wave_tick = [&]() {
+      if (STATS) {
+        if ((int)lane == __builtin_ctzll(__ballot(1))) ++st_wave;
+      }
+    };
+    auto pop_or_none = [&]() -> int32_t {
+      if (sp == 0) return kEmptyChild;
+      --sp;
+      return sp < kLdsStack ? lstack[sp * BLOCK] : spill[sp - kLdsStack];
+    };
     if (slot < 0) continue;
-    if (STATS) ++st_trips;
 
-    // ---- one traversal step
-    bool pop = true;
-    if (node >= 0 && node != kEmptyChild) {
-      if (STATS) ++st_inner;
+    // ---- inner nodes, until every lane of the wave holds a postponed leaf
+    // (or has finished), so that node tests and triangle tests do not
+    // diverge within one iteration
+    while (node >= 0 && node != kEmptyChild) {
+      wave_tick();
+      if (STATS) {
+        ++st_trips;
+        ++st_inner;
+      }
       float t0, t1, t2, t3;
       bool h0, h1, h2, h3;
       int4 cc;
+      float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];
       if constexpr (QNODE) {
         const float4* N = nodes + 4 * (size_t)node;
         const float4 a = N[0], b = N[1], c = N[2];
         cc = *reinterpret_cast<const int4*>(N + 3);
         const uint32_t eb = __float_as_uint(a.w);
-        const float sx = __uint_as_float((eb & 0xFFu) << 23);
-        const float sy = __uint_as_float(((eb >> 8) & 0xFFu) << 23);
-        const float sz = __uint_as_float(((eb >> 16) & 0xFFu) << 23);
-        const uint32_t qlx = __float_as_uint(b.x), qhx = __float_as_uint(b.y);
-        const uint32_t qly = __float_as_uint(b.z), qhy = __float_as_uint(b.w);
-        const uint32_t qlz = __float_as_uint(c.x), qhz = __float_as_uint(c.y);
-        h0 = slab(dq(a.x, qlx, 0, sx), dq(a.x, qhx, 0, sx), dq(a.y, qly, 0, sy), dq(a.y, qhy, 0, sy),
-                  dq(a.z, qlz, 0, sz), dq(a.z, qhz, 0, sz), R, tbest, &t0) && cc.x != kEmptyChild;
-        h1 = slab(dq(a.x, qlx, 1, sx), dq(a.x, qhx, 1, sx), dq(a.y, qly, 1, sy), dq(a.y, qhy, 1, sy),
-                  dq(a.z, qlz, 1, sz), dq(a.z, qhz, 1, sz), R, tbest, &t1) && cc.y != kEmptyChild;
-        h2 = slab(dq(a.x, qlx, 2, sx), dq(a.x, qhx, 2, sx), dq(a.y, qly, 2, sy), dq(a.y, qhy, 2, sy),
-                  dq(a.z, qlz, 2, sz), dq(a.z, qhz, 2, sz), R, tbest, &t2) && cc.z != kEmptyChild;
-        h3 = slab(dq(a.x, qlx, 3, sx), dq(a.x, qhx, 3, sx), dq(a.y, qly, 3, sy), dq(a.y, qhy, 3, sy),
-                  dq(a.z, qlz, 3, sz), dq(a.z, qhz, 3, sz), R, tbest, &t3) && cc.w != kEmptyChild;
+        qaxis(a.x, __uint_as_float((eb & 0xFFu) << 23), R.ox, R.ix, __float_as_uint(b.x), __float_as_uint(b.y),
+              lox, hix);
+        qaxis(a.y, __uint_as_float(((eb >> 8) & 0xFFu) << 23), R.oy, R.iy, __float_as_uint(b.z),
+              __float_as_uint(b.w), loy, hiy);
+        qaxis(a.z, __uint_as_float(((eb >> 16) & 0xFFu) << 23), R.oz, R.iz, __float_as_uint(c.x),
+              __float_as_uint(c.y), loz, hiz);
+        h0 = qslab(lox[0], hix[0], loy[0], hiy[0], loz[0], hiz[0], R.tmin, tbest, &t0) && cc.x != kEmptyChild;
+        h1 = qslab(lox[1], hix[1], loy[1], hiy[1], loz[1], hiz[1], R.tmin, tbest, &t1) && cc.y != kEmptyChild;
+        h2 = qslab(lox[2], hix[2], loy[2], hiy[2], loz[2], hiz[2], R.tmin, tbest, &t2) && cc.z != kEmptyChild;
+        h3 = qslab(lox[3], hix[3], loy[3], hiy[3], loz[3], hiz[3], R.tmin, tbest, &t3) && cc.w != kEmptyChild;
       } else {
         const float4* N = nodes + 8 * (size_t)node;
         const float4 lx = N[0], hx = N[1], ly = N[2], hy = N[3], lz = N[4], hz = N[5];
@@ -224,12 +263,27 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
           }
         }
         node = c0;
-        pop = false;
+      } else {
+        node = pop_or_none();
       }
-    } else if (node < 0) {
-      const int32_t code = ~node;
+      if (node < 0 && leaf == 0) {
+        leaf = node;
+        node = pop_or_none();
+      }
+      if (!__ballot(leaf == 0 && node >= 0 && node != kEmptyChild)) break;
+    }
+    if (node < 0 && leaf == 0) {
+      leaf = node;
+      node = pop_or_none();
+    }
+
+    // ---- the postponed leaf, then any leaves that follow on the stack
+    while (leaf < 0) {
+      wave_tick();
+      const int32_t code = ~leaf;
       const int32_t first = code >> 3, count = code & 7;
       if (STATS) {
+        ++st_trips;
         ++st_leaf;
         st_tri += (unsigned long long)count;
       }
@@ -261,15 +315,15 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
           bv = v;
         }
       }
-    }
-    if (pop) {
-      if (sp == 0) {
-        hits[slot] = make_float4(bprim >= 0 ? tbest : __int_as_float(0x7f800000), __int_as_float(bprim), bu, bv);
-        slot = -1;
-      } else {
-        --sp;
-        node = sp < kLdsStack ? lstack[sp * BLOCK] : spill[sp - kLdsStack];
+      leaf = 0;
+      if (node < 0) {
+        leaf = node;
+        node = pop_or_none();
       }
+    }
+    if (node == kEmptyChild) {
+      hits[slot] = make_float4(bprim >= 0 ? tbest : __int_as_float(0x7f800000), __int_as_float(bprim), bu, bv);
+      slot = -1;
     }
   }
   if (STATS) {
@@ -278,7 +332,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
     atomicAdd(&stats->leaves, st_leaf);
     atomicAdd(&stats->tri_tests, st_tri);
     atomicAdd(&stats->rays, st_rays);
-    if (lane == 0) atomicAdd(&stats->wave_trips64, st_wave);
+    atomicAdd(&stats->wave_trips64, 64ull * st_wave);
   }
 }
 
