@@ -7,18 +7,26 @@
 //    device (a compaction count, a batch table) and one captured launch
 //    sequence serves any mix;
 //  * k_seg_hist reads every key once and builds the digit histograms of all
-//    passes per segment; k_seg_scan turns them into absolute digit bases;
-//  * k_seg_pass blocks are persistent and take tiles in order from an atomic
-//    counter.  A tile is ranked by digit with wave64 ballots (a match over
+//    passes per segment;
+//  * k_seg_pass blocks are persistent and take tiles in a fixed order
+//    (block b: tiles b, b + G, b + 2G, ...), so no shared tile counter is
+//    contended.  A tile is ranked by digit with wave64 ballots (a match over
 //    the digit's bits gives each lane its peers; the lowest peer bumps the
 //    wave's digit counter in LDS), its digit counts are published, the
 //    previous tiles of the same segment are looked back for the global
 //    offsets (decoupled look-back, Merrill and Garland 2016), and the tile is
 //    reordered in LDS and written as contiguous digit runs.
+//  * The look-back is two-level: tiles form groups of kGroup, and the last
+//    tile of a group also publishes the group's total and then its inclusive
+//    prefix, so a tile reads its own group's tiles and then whole groups,
+//    kGroup tiles per word.
+//  * Waits never depend on other blocks being resident: an entry that stays
+//    unpublished for kFallbackSpins polls is computed by the waiting thread
+//    itself from the input keys (the fallback of decoupled look-back, Smith,
+//    Levien and Owens 2024), so every wait ends.
 // Ranking keeps input order within a digit, so the sort is stable and the
 // output is the unique (key, index) lexicographic order for ascending input
-// indices.  Look-back waits are bounded: a wait that exceeds its limit sets
-// an error word instead of hanging.
+// indices.
 #include <algorithm>
 #include <utility>
 
@@ -30,8 +38,8 @@ namespace {
 
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / kWave;
-constexpr uint32_t kSpinLimit = 1u << 18;
-constexpr int kLookback = 16;  // predecessors read per look-back round trip
+constexpr uint32_t kGroup = 16;          // tiles per look-back group
+constexpr uint32_t kFallbackSpins = 128; // polls of one unpublished entry before computing it
 constexpr uint32_t kHistUnit = 4096;  // keys per histogram work unit (16 per thread)
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
@@ -73,35 +81,38 @@ __device__ __forceinline__ uint32_t seg_of_tile(const SortSeg* segs, uint32_t ns
   return lo;
 }
 
-// One segment of n = min(*count_dev, n_max) keys.
+// One segment of n = min(*count_dev, n_max) keys; clears its histograms.
 __global__ void k_seg_setup_single(const uint32_t* count_dev, uint32_t n_max, uint32_t tile, SortHdr* hdr,
-                                   SortSeg* segs) {
-  if (threadIdx.x != 0) return;
-  uint32_t n = n_max;
-  if (count_dev) n = min(*count_dev, n_max);
-  const uint32_t tiles = (n + tile - 1) / tile;
-  segs[0] = SortSeg{0u, n, 0u, tiles};
-  *hdr = SortHdr{1u, tiles, n, 0u};
+                                   SortSeg* segs, uint32_t* __restrict__ hist, uint32_t hist_words) {
+  if (threadIdx.x == 0) {
+    uint32_t n = n_max;
+    if (count_dev) n = min(*count_dev, n_max);
+    const uint32_t tiles = (n + tile - 1) / tile;
+    segs[0] = SortSeg{0u, n, 0u, tiles};
+    *hdr = SortHdr{1u, tiles, n, 0u};
+  }
+  for (uint32_t i = threadIdx.x; i < hist_words; i += blockDim.x) hist[i] = 0;
 }
 
-__global__ void k_seg_init(const SortHdr* hdr, uint32_t* __restrict__ hist, uint32_t words_per_seg,
-                           uint32_t* __restrict__ counters, uint32_t n_counters) {
+// Clears the histograms of a segment table set up by the caller.
+__global__ void k_seg_init(const SortHdr* hdr, uint32_t* __restrict__ hist, uint32_t words_per_seg) {
   const uint32_t n = hdr->nseg * words_per_seg;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) hist[i] = 0;
-  if (blockIdx.x == 0)
-    for (uint32_t i = threadIdx.x; i < n_counters; i += blockDim.x) counters[i] = 0;
 }
 
 // Digit histograms of every pass per segment.  Blocks take contiguous runs
 // of kHistUnit-key units (a unit never straddles a segment), load a unit's
 // keys before counting them, and flush their LDS counts when the segment
-// changes; the look-back words the passes will use are cleared too.
+// changes; the look-back words (tile and group) the passes will use are
+// cleared too.
 template <typename K, int DB, int KPT>
 __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__ keys, const SortHdr* hdr,
                                                            const SortSeg* __restrict__ segs, uint32_t passes,
                                                            uint32_t* __restrict__ hist,
                                                            uint32_t* __restrict__ status,
-                                                           uint32_t status_pass_stride) {
+                                                           uint32_t status_pass_stride,
+                                                           uint32_t* __restrict__ gstatus,
+                                                           uint32_t gstatus_pass_stride) {
   constexpr uint32_t R = 1u << DB;
   constexpr uint32_t kTile = kSortThreads * KPT;
   constexpr uint32_t kUnitsPerTile = kTile >= kHistUnit ? kTile / kHistUnit : 1u;
@@ -151,27 +162,15 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
   if (u0 < u1)
     for (uint32_t i = threadIdx.x; i < words; i += kSortThreads)
       if (s_h[i]) atomicAdd(&hist[(size_t)cur * words + i], s_h[i]);
-  // clear the look-back words of the tiles this sort will use
+  // clear the look-back words of the tiles and groups this sort will use
   const uint32_t stride = gridDim.x * kSortThreads;
-  for (uint32_t p = 0; p < passes; ++p)
+  const uint32_t groups = T / kGroup + nseg;
+  for (uint32_t p = 0; p < passes; ++p) {
     for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < T * R; i += stride)
       status[(size_t)p * status_pass_stride + i] = 0;
-}
-
-// hist[s][p][d] -> segment offset + exclusive prefix over d: the first
-// output slot of digit d in pass p.  One block per (segment, pass).
-template <int DB>
-__global__ __launch_bounds__(kSortThreads) void k_seg_scan(const SortHdr* hdr, const SortSeg* __restrict__ segs,
-                                                           uint32_t passes, uint32_t* __restrict__ hist) {
-  constexpr uint32_t R = 1u << DB;
-  __shared__ uint32_t s[kSortWaves];
-  const uint32_t seg = blockIdx.x / passes, p = blockIdx.x % passes;
-  if (seg >= hdr->nseg) return;  // block-uniform
-  uint32_t* h = hist + ((size_t)seg * passes + p) * R;
-  const uint32_t v = threadIdx.x < R ? h[threadIdx.x] : 0u;
-  uint32_t total;
-  const uint32_t ex = block_scan_256(v, s, &total);
-  if (threadIdx.x < R) h[threadIdx.x] = segs[seg].off + ex;
+    for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < groups * R; i += stride)
+      gstatus[(size_t)p * gstatus_pass_stride + i] = 0;
+  }
 }
 
 template <typename K, int DB, int KPT>
@@ -183,9 +182,136 @@ struct PassSmem {
   uint32_t wave_hist[kSortWaves][R];
   uint32_t local_off[R];
   uint32_t global_off[R];
+  uint32_t base[R];
   uint32_t scan[kSortWaves];
-  uint32_t tile;
 };
+
+__device__ __forceinline__ uint32_t load_status(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_status(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Number of keys with digit d in local tile lt of segment sg, counted from
+// the input: what that tile's owner publishes, for the look-back fallback.
+template <typename K, uint32_t kTile>
+__device__ __noinline__ uint32_t count_digit(const K* __restrict__ keys_in, SortSeg sg, uint32_t lt, uint32_t shift,
+                                             uint32_t mask, uint32_t d) {
+  const uint32_t first = sg.off + lt * kTile;
+  const uint32_t n = min(kTile, sg.n - lt * kTile);
+  uint32_t c = 0;
+  for (uint32_t i = 0; i < n; ++i) c += ((uint32_t)(keys_in[first + i] >> shift) & mask) == d ? 1u : 0u;
+  return c;
+}
+
+// Published value of local tile lt for digit d, waiting for it at most
+// kFallbackSpins polls and counting it from the input after that.
+template <typename K, uint32_t kTile>
+__device__ uint32_t tile_word(const uint32_t* status, const K* __restrict__ keys_in, SortSeg sg, uint32_t lt,
+                              uint32_t R, uint32_t shift, uint32_t d) {
+  for (uint32_t spins = 0; spins < kFallbackSpins; ++spins) {
+    const uint32_t w = load_status(&status[(size_t)(sg.tile_off + lt) * R + d]);
+    if (w & ~kStatusCountMask) return w;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return kStatusAggregate | count_digit<K, kTile>(keys_in, sg, lt, shift, R - 1, d);
+}
+
+// Exclusive prefix of digit d before local tile lt (lt > 0) of segment sg,
+// whose own count is c.  Phase A sums the published words of the earlier
+// tiles of lt's group, nearest first, up to an inclusive one; phase B
+// continues over whole groups.  A group word still unpublished after the
+// wait limit is replaced by its tiles' words, and a tile word by a count
+// from the input.  The last tile of a group passes its group word as gword:
+// when phase A ends without an inclusive word, the group total is published
+// there before phase B.
+template <typename K, uint32_t kTile>
+__device__ uint32_t look_back(const uint32_t* status, const uint32_t* gstatus, const K* __restrict__ keys_in,
+                              SortSeg sg, uint32_t gbase, uint32_t lt, uint32_t R, uint32_t shift, uint32_t d,
+                              uint32_t c, uint32_t* gword) {
+  const uint32_t g = lt / kGroup, gs = g * kGroup;
+  uint32_t acc = 0;
+  bool done = false;
+  uint32_t spins = 0;
+  int32_t j = (int32_t)lt - 1;  // nearest tile not yet accounted for
+  while (!done && j >= (int32_t)gs) {
+    const int32_t lim = j - (int32_t)gs + 1;  // valid entries in the window
+    uint32_t w[kGroup - 1];
+#pragma unroll
+    for (int q = 0; q < (int)kGroup - 1; ++q)
+      w[q] = q < lim ? load_status(&status[(size_t)(sg.tile_off + j - q) * R + d]) : 0u;
+    uint32_t a = 0;
+    int used = 0;
+    bool blocked = false;
+#pragma unroll
+    for (int q = 0; q < (int)kGroup - 1; ++q) {
+      if (done || blocked || q >= lim) continue;
+      const uint32_t flag = w[q] & ~kStatusCountMask;
+      if (flag == 0) {
+        blocked = true;
+      } else {
+        a += w[q] & kStatusCountMask;
+        ++used;
+        if (flag == kStatusPrefix) done = true;
+      }
+    }
+    acc += a;
+    j -= used;
+    if (blocked) {
+      if (++spins >= kFallbackSpins) {
+        acc += count_digit<K, kTile>(keys_in, sg, (uint32_t)j, shift, R - 1, d);
+        --j;
+        spins = 0;
+      } else {
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+  }
+  if (gword && !done) store_status(gword, kStatusAggregate | (acc + c));
+  int32_t G = (int32_t)g - 1;  // nearest group not yet accounted for
+  spins = 0;
+  while (!done && G >= 0) {
+    const int32_t lim = G + 1;
+    uint32_t w[kGroup];
+#pragma unroll
+    for (int q = 0; q < (int)kGroup; ++q)
+      w[q] = q < lim ? load_status(&gstatus[(size_t)(gbase + G - q) * R + d]) : 0u;
+    uint32_t a = 0;
+    int used = 0;
+    bool blocked = false;
+#pragma unroll
+    for (int q = 0; q < (int)kGroup; ++q) {
+      if (done || blocked || q >= lim) continue;
+      const uint32_t flag = w[q] & ~kStatusCountMask;
+      if (flag == 0) {
+        blocked = true;
+      } else {
+        a += w[q] & kStatusCountMask;
+        ++used;
+        if (flag == kStatusPrefix) done = true;
+      }
+    }
+    acc += a;
+    G -= used;
+    if (blocked) {
+      if (++spins >= kFallbackSpins) {
+        // the group's last tile has not published: read its tiles instead
+        for (int32_t t = G * (int32_t)kGroup + (int32_t)kGroup - 1; t >= G * (int32_t)kGroup && !done; --t) {
+          const uint32_t v = tile_word<K, kTile>(status, keys_in, sg, (uint32_t)t, R, shift, d);
+          acc += v & kStatusCountMask;
+          if ((v & ~kStatusCountMask) == kStatusPrefix) done = true;
+        }
+        --G;
+        spins = 0;
+      } else {
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+  }
+  return acc;
+}
 
 template <typename K, int DB, int KPT>
 __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__ keys_in,
@@ -194,33 +320,25 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
                                                            const SortHdr* hdr, const SortSeg* __restrict__ segs,
                                                            uint32_t shift, uint32_t passes, uint32_t pass,
                                                            const uint32_t* __restrict__ hist,
-                                                           uint32_t* __restrict__ status, uint32_t* tile_counter,
-                                                           uint32_t* err) {
+                                                           uint32_t* __restrict__ status,
+                                                           uint32_t* __restrict__ gstatus) {
   using S = PassSmem<K, DB, KPT>;
   constexpr uint32_t R = S::R;
   constexpr uint32_t kTile = S::kTile;
   __shared__ S sm;
   const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const uint32_t nseg = hdr->nseg, T = hdr->total_tiles;
+  uint32_t cur = 0xFFFFFFFFu;  // segment whose digit bases are in sm.base
 
-  while (true) {
-    __syncthreads();  // the previous tile is fully written out
-    if (tid == 0) sm.tile = atomicAdd(tile_counter, 1u);
-    for (uint32_t i = tid; i < kSortWaves * R; i += kSortThreads) (&sm.wave_hist[0][0])[i] = 0;
-    __syncthreads();
-    const uint32_t tile = sm.tile;
-    if (tile >= T) break;  // block-uniform
-    const uint32_t s = seg_of_tile(segs, nseg, tile);
-    const SortSeg sg = segs[s];
-    const uint32_t tile_in = tile - sg.tile_off;
-    const uint32_t base = sg.off + tile_in * kTile;
-    const uint32_t tile_n = min(kTile, sg.n - tile_in * kTile);
-    const uint32_t* digit_base = hist + ((size_t)s * passes + pass) * R;
+  for (uint32_t i = tid; i < kSortWaves * R; i += kSortThreads) (&sm.wave_hist[0][0])[i] = 0;
 
-    // ---- load (wave-striped: wave w owns KPT consecutive groups of 64)
-    K k[KPT];
-    uint32_t v[KPT];
-    uint32_t rank[KPT];
+  // Keys and indices of a tile, loaded wave-striped: wave w owns KPT
+  // consecutive groups of 64.  The next tile's loads are issued before the
+  // current tile is written out, so their latency overlaps the writes.
+  K k[KPT];
+  uint32_t v[KPT];
+  uint32_t rank[KPT];
+  auto load_tile = [&](uint32_t base, uint32_t tile_n) {
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       const uint32_t pos = wave * (KPT * kWave) + j * kWave + lane;
@@ -228,6 +346,20 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
       k[j] = ok ? keys_in[base + pos] : (K)0;
       v[j] = ok ? idx_in[base + pos] : 0u;
     }
+  };
+  uint32_t tile = blockIdx.x;
+  uint32_t s = 0;
+  SortSeg sg{};
+  if (tile < T) {
+    s = seg_of_tile(segs, nseg, tile);
+    sg = segs[s];
+    const uint32_t lt = tile - sg.tile_off;
+    load_tile(sg.off + lt * kTile, min(kTile, sg.n - lt * kTile));
+  }
+  while (tile < T) {  // block-uniform
+    const uint32_t lt = tile - sg.tile_off;
+    const uint32_t tile_n = min(kTile, sg.n - lt * kTile);
+    __syncthreads();  // the previous tile's LDS reads are done; wave_hist is clear
 
     // ---- rank within the wave, in (j, lane) order
 #pragma unroll
@@ -254,9 +386,19 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
     }
     __syncthreads();
 
+    // ---- digit bases of this segment and pass: offset + exclusive prefix
+    if (s != cur) {  // block-uniform
+      uint32_t total;
+      const uint32_t h = tid < R ? hist[((size_t)s * passes + pass) * R + tid] : 0u;
+      const uint32_t ex = block_scan_256(h, sm.scan, &total);
+      if (tid < R) sm.base[tid] = sg.off + ex;
+      cur = s;
+    }
+
     // ---- per digit: wave offsets, tile count, publication
     uint32_t count = 0;
-    for (uint32_t d = tid; d < R; d += kSortThreads) {
+    if (tid < R) {
+      const uint32_t d = tid;
       uint32_t c = 0;
 #pragma unroll
       for (int w = 0; w < kSortWaves; ++w) {
@@ -265,60 +407,25 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
         c += t;
       }
       count = c;
-      const uint32_t word = (tile_in == 0 ? kStatusPrefix : kStatusAggregate) | c;
-      __hip_atomic_store(&status[(size_t)tile * R + d], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      store_status(&status[(size_t)tile * R + d], (lt == 0 ? kStatusPrefix : kStatusAggregate) | c);
     }
     uint32_t total;
-    const uint32_t local = block_scan_256(tid < R ? count : 0u, sm.scan, &total);
+    const uint32_t local = block_scan_256(count, sm.scan, &total);
     if (tid < R) sm.local_off[tid] = local;
 
-    // ---- decoupled look-back over this segment's earlier tiles, reading a
-    // window of kLookback predecessors per round trip: aggregates are summed
-    // up to the nearest published prefix; an unpublished entry is waited on.
+    // ---- look-back for the global offsets
     if (tid < R) {
       const uint32_t d = tid;
+      const uint32_t gbase = sg.tile_off / kGroup + s;  // group words of this segment
+      const bool last_of_group = (lt % kGroup) == kGroup - 1;
       uint32_t prefix = 0;
-      if (tile_in > 0) {
-        int64_t j = (int64_t)tile - 1;  // nearest tile not yet accounted for
-        uint32_t spins = 0;
-        while (j >= (int64_t)sg.tile_off) {
-          uint32_t w[kLookback];
-#pragma unroll
-          for (int q = 0; q < kLookback; ++q)
-            w[q] = (j - q >= (int64_t)sg.tile_off)
-                       ? __hip_atomic_load(&status[(size_t)(j - q) * R + d], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT)
-                       : kStatusPrefix;  // below the segment: acts as a zero prefix
-          uint32_t acc = 0;
-          int used = 0;
-          bool found = false, blocked = false;
-#pragma unroll
-          for (int q = 0; q < kLookback; ++q) {
-            if (found || blocked) continue;
-            const uint32_t flag = w[q] & ~kStatusCountMask;
-            if (flag == 0) {
-              blocked = true;
-            } else {
-              acc += w[q] & kStatusCountMask;
-              ++used;
-              if (flag == kStatusPrefix) found = true;
-            }
-          }
-          prefix += acc;
-          if (found) break;
-          j -= used;
-          if (blocked) {
-            if (++spins > kSpinLimit) {
-              atomicOr(err, 1u);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-          }
-        }
-        __hip_atomic_store(&status[(size_t)tile * R + d], kStatusPrefix | (prefix + count), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+      uint32_t* gword = last_of_group ? &gstatus[(size_t)(gbase + lt / kGroup) * R + d] : nullptr;
+      if (lt > 0) {
+        prefix = look_back<K, kTile>(status, gstatus, keys_in, sg, gbase, lt, R, shift, d, count, gword);
+        store_status(&status[(size_t)tile * R + d], kStatusPrefix | (prefix + count));
       }
-      sm.global_off[d] = digit_base[d] + prefix;
+      if (gword) store_status(gword, kStatusPrefix | (prefix + count));
+      sm.global_off[d] = sm.base[d] + prefix;
     }
     __syncthreads();
 
@@ -336,9 +443,17 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
       }
     }
     __syncthreads();
+    for (uint32_t i = tid; i < kSortWaves * R; i += kSortThreads) (&sm.wave_hist[0][0])[i] = 0;
 
-    // ---- write digit runs contiguously
+    // ---- prefetch the next tile, then write this one's digit runs
     const uint32_t seg_end = sg.off + sg.n;
+    const uint32_t next = tile + gridDim.x;
+    const uint32_t s_next = next < T ? seg_of_tile(segs, nseg, next) : s;
+    const SortSeg sg_next = next < T ? segs[s_next] : sg;
+    if (next < T) {
+      const uint32_t lt_next = next - sg_next.tile_off;
+      load_tile(sg_next.off + lt_next * kTile, min(kTile, sg_next.n - lt_next * kTile));
+    }
     for (uint32_t p = tid; p < tile_n; p += kSortThreads) {
       const K key = sm.keys[p];
       const uint32_t d = (uint32_t)(key >> shift) & (R - 1);
@@ -348,6 +463,9 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
         idx_out[out] = sm.idx[p];
       }
     }
+    tile = next;
+    s = s_next;
+    sg = sg_next;
   }
 }
 
@@ -383,25 +501,25 @@ rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, So
   SortHdr* hdr = single ? reinterpret_cast<SortHdr*>(ws + L.hdr) : hdr_ext;
   SortSeg* segs = single ? reinterpret_cast<SortSeg*>(ws + L.segs) : segs_ext;
   uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
-  uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
-  uint32_t* err = counters + L.passes;
   uint32_t* status = reinterpret_cast<uint32_t*>(ws + L.status);
+  uint32_t* gstatus = reinterpret_cast<uint32_t*>(ws + L.gstatus);
 
   const uint32_t hist_res = Resident<K, DB, KPT>::hist();
   const uint32_t pass_res = Resident<K, DB, KPT>::pass();
   const uint32_t max_tiles = L.max_tiles;
   if (single)
-    hipLaunchKernelGGL(k_seg_setup_single, dim3(1), dim3(64), 0, st, count_dev, n_max, L.tile, hdr, segs);
-  hipLaunchKernelGGL(k_seg_init, dim3(std::max(1u, std::min(64u, L.max_seg))), dim3(256), 0, st, hdr, hist,
-                     L.passes * R, counters, L.passes + 1);
+    hipLaunchKernelGGL(k_seg_setup_single, dim3(1), dim3(256), 0, st, count_dev, n_max, L.tile, hdr, segs, hist,
+                       L.passes * R);
+  else
+    hipLaunchKernelGGL(k_seg_init, dim3(std::max(1u, std::min(64u, L.max_seg))), dim3(256), 0, st, hdr, hist,
+                       L.passes * R);
   // about one unit per block: each block flushes its whole histogram with
   // global atomics, so more blocks than units only adds flush traffic
   const uint32_t hist_units = std::max(1u, max_tiles * L.tile / kHistUnit);
   const uint32_t hist_blocks = std::max(1u, std::min(hist_units, std::min(hist_res, 1024u)));
   hipLaunchKernelGGL((k_seg_hist<K, DB, KPT>), dim3(hist_blocks), dim3(kSortThreads), 0, st, keys, hdr, segs,
-                     L.passes, hist, status, L.status_stride);
-  hipLaunchKernelGGL((k_seg_scan<DB>), dim3(L.max_seg * L.passes), dim3(kSortThreads), 0, st, hdr, segs, L.passes,
-                     hist);
+                     L.passes, hist, status, L.status_stride, gstatus, L.gstatus_stride);
+  // one resident wave of blocks: block b takes tiles b, b + G, ...
   const uint32_t pass_blocks = std::max(1u, std::min(max_tiles, pass_res));
   K* src_k = keys;
   uint32_t* src_i = idx;
@@ -410,7 +528,7 @@ rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, So
   for (uint32_t p = 0; p < L.passes; ++p) {
     hipLaunchKernelGGL((k_seg_pass<K, DB, KPT>), dim3(pass_blocks), dim3(kSortThreads), 0, st, src_k, src_i, dst_k,
                        dst_i, hdr, segs, p * DB, L.passes, p, hist, status + (size_t)p * L.status_stride,
-                       counters + p, err);
+                       gstatus + (size_t)p * L.gstatus_stride);
     std::swap(src_k, dst_k);
     std::swap(src_i, dst_i);
   }
@@ -437,8 +555,11 @@ SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_
   L.hdr = off; off = align_up(off + sizeof(SortHdr), 256);
   L.segs = off; off = align_up(off + sizeof(SortSeg) * max_seg, 256);
   L.hist = off; off = align_up(off + 4 * (size_t)max_seg * L.passes * R, 256);
-  L.counters = off; off = align_up(off + 4 * (L.passes + 1), 256);  // tile counters, then the error word
   L.status = off; off = align_up(off + 4 * (size_t)L.passes * L.status_stride, 256);
+  // group words: group g of a segment whose first tile is t0 and index s
+  // sits at t0 / kGroup + s + g, below max_tiles / kGroup + max_seg
+  L.gstatus_stride = (uint32_t)((L.max_tiles / kGroup + max_seg + 1) * R);
+  L.gstatus = off; off = align_up(off + 4 * (size_t)L.passes * L.gstatus_stride, 256);
   L.total = off;
   return L;
 }

@@ -17,8 +17,8 @@ struct SortHdr {
 };
 
 struct SegLayout {
-  size_t keys_alt, idx_alt, hdr, segs, hist, counters, status, total;
-  uint32_t passes, tile, max_seg, max_tiles, status_stride;
+  size_t keys_alt, idx_alt, hdr, segs, hist, status, gstatus, total;
+  uint32_t passes, tile, max_seg, max_tiles, status_stride, gstatus_stride;
 };
 
 SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_t db, uint32_t kpt);
