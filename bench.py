@@ -20,6 +20,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -35,6 +36,13 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "MRays/s incl. reorder vs unsorted trace; sort GB/s; p50/p99 batch latency"
 KEYS = {"none": (0, 32), "od32": (1, 32), "od64": (1, 64), "ot32": (2, 32), "ot64": (2, 64)}
+# HBM traffic of the sorted trace launch, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes scaled by a plain copy's readings; valid only while the sources that
+# decide the trace's memory traffic are unchanged (checked by digest).
+TRAFFIC_PROFILE = os.path.join("profiles", "k_trace4_bounce2_1080p_traffic.txt")
+TRAFFIC_SOURCES = ("paper_2506_11273_amd/csrc/trace.hip", "paper_2506_11273_amd/csrc/scene.cpp",
+                   "paper_2506_11273_amd/csrc/common.hpp", "paper_2506_11273_amd/csrc/keys_dev.hpp",
+                   "paper_2506_11273_amd/csrc/keys.hip", "workloads/gen.c")
 SECTIONS = ("variants", "bounce3", "batch", "serve", "cpu")
 
 
@@ -143,7 +151,8 @@ def main():
         torch.cuda.synchronize()
         if args.copy_calibration:
             copy_calibration(torch, dev)
-        print(json.dumps({"phases": "trace", "steps": args.steps}))
+        print(json.dumps({"phases": "trace", "steps": args.steps, "warmup": args.warmup,
+                          "sources_sha256": sources_digest()}))
         return
 
     for _ in range(args.warmup):
@@ -203,7 +212,7 @@ def main():
         "per_ray": {"inner_visits": round(prof["inner_visits"] / n, 2), "leaf_visits": round(prof["leaf_visits"] / n, 2),
                     "tri_tests": round(prof["tri_tests"] / n, 2)},
         "hits_scatter_back_equal_unsorted": same,
-        "roofline": trace_roofline(trace_bytes, trace_ms, n),
+        "roofline": trace_roofline(trace_bytes, trace_ms, n, profiled_traffic(args.key, args.builder)),
     }
     if "variants" not in args.skip:
         result["variants"] = variants(torch, rr, scene, rays, n, lo, hi, dev, stream, args.steps, unsorted_ms)
@@ -225,11 +234,38 @@ def main():
     print(json.dumps(result))
 
 
-def trace_roofline(trace_bytes, trace_ms, n):
+def sources_digest() -> str:
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        h.update(rel.encode())
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(key: str, builder: int):
+    """Bytes per sorted-trace launch from the committed counter summary, or
+    None when it was taken on other sources or another configuration."""
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_PROFILE)) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(" "))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("sources_sha256") != sources_digest() or kv.get("key") != key or kv.get("builder") != str(builder):
+        return None
+    try:
+        return int(kv["traffic_bytes_per_launch_sorted"])
+    except (KeyError, ValueError):
+        return None
+
+
+def trace_roofline(trace_bytes, trace_ms, n, traffic):
     return {"kernel": "k_trace4 (sorted rays)", "bound": "hbm",
             "achieved": round(trace_bytes / (trace_ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(trace_bytes / (trace_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
-            "traffic": None, "algorithmic_bytes_per_ray": 48, "launch_ms": round(trace_ms, 4)}
+            "traffic": traffic, "algorithmic_bytes_per_launch": trace_bytes, "algorithmic_bytes_per_ray": 48,
+            "launch_ms": round(trace_ms, 4)}
 
 
 def variants(torch, rr, scene, rays, n, lo, hi, dev, stream, steps, unsorted_ms):
