@@ -8,7 +8,12 @@ Reordering Techniques for Faster GPU Ray Tracing", I3D 2020) directly:
 
 * keys            -- Section 3.1 and Figure "codes": origin-direction
                      (Reis) and Two Point (origin-termination) keys with the
-                     fixed-length termination estimate (Section 3.1.6).
+                     fixed-length termination estimate (Section 3.1.6), the
+                     figure's other layouts (Origin, Costa, Aila, Aila
+                     Compact, Octahedron), and Two Point with the adaptive
+                     (length table) or real (traced) termination point.
+* LengthTable     -- Section 3.1.6: the 2^20-cell table of mean traced
+                     lengths keyed by the 20-bit Aila Compact code.
 * sort_pairs      -- Section 3.2: key/index pairs sorted by key; the
                      stable order is the lexicographic order of (key, index).
 * gather          -- Section 3.2: "an additional pass" moving the ray data.
@@ -33,6 +38,11 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 KIND_NONE, KIND_OD, KIND_OT = 0, 1, 2
+KIND_ORIGIN, KIND_COSTA, KIND_AILA, KIND_AILA_COMPACT, KIND_OCTAHEDRON = 3, 4, 5, 6, 7
+KIND_TP_ADAPTIVE, KIND_TP_REAL = 8, 9
+KIND_CODE20 = 100
+CELL_DTYPE = np.dtype([("sum", np.uint64), ("count", np.uint32), ("unused", np.uint32)])
+N_CELLS = 1 << 20
 HIT_DTYPE = np.dtype([("t", np.float32), ("prim", np.int32), ("u", np.float32), ("v", np.float32)])
 DEFAULT_THREADS = min(16, os.cpu_count() or 1)
 
@@ -55,7 +65,12 @@ def _get():
             build(force=True)
         L = ctypes.CDLL(_LIB)
         vp, i64, i32, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float
-        L.orc_keys.argtypes = [vp, i64, i32, i32, vp, vp, f32, i32, vp]; L.orc_keys.restype = ctypes.c_int
+        L.orc_keys.argtypes = [vp, i64, i32, i32, vp, vp, f32, i32, vp, vp]; L.orc_keys.restype = ctypes.c_int
+        L.orc_octahedral.argtypes = [vp, vp, vp]; L.orc_octahedral.restype = None
+        L.orc_cell_code.argtypes = [vp, vp, vp]; L.orc_cell_code.restype = ctypes.c_uint32
+        L.orc_len_init.argtypes = [vp, f32]; L.orc_len_init.restype = None
+        L.orc_len_accumulate.argtypes = [vp, vp, vp, i64, vp, vp]; L.orc_len_accumulate.restype = None
+        L.orc_len_lookup.argtypes = [vp, vp, vp, vp]; L.orc_len_lookup.restype = f32
         L.orc_key_layout.argtypes = [i32, i32, i32, vp, vp]; L.orc_key_layout.restype = ctypes.c_int
         L.orc_mt.argtypes = [vp, vp, vp, vp, vp, vp]; L.orc_mt.restype = ctypes.c_int
         L.orc_brute_force.argtypes = [vp, i64, vp, i64, vp, i32]; L.orc_brute_force.restype = None
@@ -81,7 +96,7 @@ def _p(a: np.ndarray) -> int:
 
 def key_layout(kind: int, key_bits: int, origin_bits: int = 0):
     """(src, comp) per key bit, MSB first; src 0 = origin, 1 = direction,
-    2 = termination point."""
+    2 = termination point, 3 = octahedral direction (u, v), -1 = zero."""
     src = np.zeros(key_bits, np.int8)
     comp = np.zeros(key_bits, np.int8)
     rc = _get().orc_key_layout(kind, key_bits, origin_bits, _p(src), _p(comp))
@@ -90,18 +105,74 @@ def key_layout(kind: int, key_bits: int, origin_bits: int = 0):
     return src, comp
 
 
-def keys(rays, kind: int, key_bits: int, box_lo, box_hi, ratio: float = 0.25, origin_bits: int = 0) -> np.ndarray:
+def keys(rays, kind: int, key_bits: int, box_lo, box_hi, ratio: float = 0.25, origin_bits: int = 0,
+         aux=None) -> np.ndarray:
     """Sort keys of rays (N, 8) float32; uint32 for 32-bit keys, uint64 for
-    64-bit keys."""
+    64-bit keys.  aux: a LengthTable (Two Point Adaptive) or the rays' hits,
+    HIT_DTYPE (Two Point Real)."""
     r = _c(rays, np.float32).reshape(-1, 8)
     lo = _c(box_lo, np.float32)
     hi = _c(box_hi, np.float32)
     out = np.empty(r.shape[0], np.uint64)
+    a = None
+    if kind == KIND_TP_ADAPTIVE:
+        a = aux.cells
+    elif kind == KIND_TP_REAL:
+        a = np.ascontiguousarray(aux, dtype=HIT_DTYPE)
+        if a.shape[0] != r.shape[0]:
+            raise ValueError("one hit per ray")
     rc = _get().orc_keys(_p(r), r.shape[0], kind, key_bits, _p(lo), _p(hi), float(np.float32(ratio)), origin_bits,
-                         _p(out))
+                         _p(a) if a is not None else None, _p(out))
     if rc != 0:
         raise ValueError("bad key parameters")
     return out.astype(np.uint32) if key_bits == 32 else out
+
+
+def octahedral(dirs) -> np.ndarray:
+    """Octahedral coordinates (u, v) in [-1, 1]^2 of directions (N, 3)."""
+    d = _c(dirs, np.float32).reshape(-1, 3)
+    out = np.empty((d.shape[0], 2), np.float32)
+    u = ctypes.c_float()
+    v = ctypes.c_float()
+    L = _get()
+    for i in range(d.shape[0]):
+        L.orc_octahedral(_p(d[i]), ctypes.byref(u), ctypes.byref(v))
+        out[i] = (u.value, v.value)
+    return out
+
+
+def cell_code(rays, box_lo, box_hi) -> np.ndarray:
+    """20-bit length-table cell of each ray (the Aila Compact prefix)."""
+    r = _c(rays, np.float32).reshape(-1, 8)
+    lo = _c(box_lo, np.float32)
+    hi = _c(box_hi, np.float32)
+    L = _get()
+    return np.array([L.orc_cell_code(_p(r[i]), _p(lo), _p(hi)) for i in range(r.shape[0])], np.uint32)
+
+
+class LengthTable:
+    """Two Point Adaptive length table (Section 3.1.6): 2^20 cells of
+    {sum of fixed-point lengths, count}, each starting with one dummy ray
+    of length ratio x the largest box extent."""
+
+    def __init__(self, box_lo, box_hi, ratio: float = 0.25):
+        self.lo = _c(box_lo, np.float32)
+        self.hi = _c(box_hi, np.float32)
+        self.cells = np.zeros(N_CELLS, CELL_DTYPE)
+        _get().orc_len_init(_p(self.cells), float(np.float32(ratio)))
+
+    def accumulate(self, rays, hits):
+        r = _c(rays, np.float32).reshape(-1, 8)
+        h = np.ascontiguousarray(hits, dtype=HIT_DTYPE)
+        if h.shape[0] != r.shape[0]:
+            raise ValueError("one hit per ray")
+        _get().orc_len_accumulate(_p(self.cells), _p(r), _p(h), r.shape[0], _p(self.lo), _p(self.hi))
+
+    def lookup(self, rays) -> np.ndarray:
+        r = _c(rays, np.float32).reshape(-1, 8)
+        L = _get()
+        return np.array([L.orc_len_lookup(_p(self.cells), _p(r[i]), _p(self.lo), _p(self.hi))
+                         for i in range(r.shape[0])], np.float32)
 
 
 def scene_box(tris):

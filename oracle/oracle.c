@@ -39,10 +39,25 @@
  *    extent of the quantisation box, quantised in that same box;
  *  - 64-bit layouts extend the 32-bit ones: origin-direction with 44 origin
  *    slots then 20 direction slots, Two Point with the same 6-cycle for 64
- *    slots.
+ *    slots.  The other layouts of the figure exist at 32 bits only (the
+ *    paper's method comparison uses 32-bit keys, Section 4.1).
+ *
+ * Layouts of the figure, as runs of slots (each run cycles x, y, z, or u, v
+ * for the octahedral direction):
+ *  Origin (3)        o32
+ *  Costa (4)         d8 o24                   direction first (Section 3.1.3)
+ *  Aila (5)          (o3 d3) x 5, o2, where every direction component's first
+ *                    three slots are zeros (Section 3.1.4: three leading
+ *                    zero bits per direction component)
+ *  Aila Compact (6)  o12 d3 o3 d3 o3 d3 o3 d2
+ *  Octahedron (7)    o15 q2 o3 q2 o3 q2 o3 q2, q = octahedral (u, v)
+ *  Two Point Adaptive (8) and Two Point Real (9): the Two Point layout, with
+ *                    the length taken from the length table or from the
+ *                    traced hit (Section 3.1.6).
  */
 
-enum { SRC_ZERO = -1, SRC_O = 0, SRC_D = 1, SRC_T = 2 };
+enum { SRC_ZERO = -1, SRC_O = 0, SRC_D = 1, SRC_T = 2, SRC_Q = 3 };
+enum { KIND_CODE20 = 100 };
 
 typedef struct {
   int n;          /* slots */
@@ -60,7 +75,15 @@ static void lay_cycle(orc_layout* L, int count, int nsrc, const int8_t* vec, con
   }
 }
 
-/* kind 1 = origin-direction, 2 = Two Point (origin-termination). */
+/* A run of `count` slots of one vector, cycling its components from x. */
+static void lay_run(orc_layout* L, int src, int count) {
+  static const int8_t xyz[3] = {0, 1, 2};
+  int8_t v[3] = {(int8_t)src, (int8_t)src, (int8_t)src};
+  lay_cycle(L, count, src == SRC_Q ? 2 : 3, v, xyz);
+}
+
+/* kind 1 = origin-direction, 2 = Two Point (origin-termination), 3-9 and
+ * KIND_CODE20 as listed above. */
 static int make_layout(int kind, int key_bits, int origin_bits, orc_layout* L) {
   memset(L, 0, sizeof *L);
   static const int8_t xyz[3] = {0, 1, 2};
@@ -72,13 +95,55 @@ static int make_layout(int kind, int key_bits, int origin_bits, orc_layout* L) {
     lay_cycle(L, key_bits - ob, 3, vd, xyz);
     return 0;
   }
-  if (kind == 2) {
+  if (kind == 2 || kind == 8 || kind == 9) {
     int8_t v6[6] = {SRC_O, SRC_O, SRC_O, SRC_T, SRC_T, SRC_T};
     int8_t c6[6] = {0, 1, 2, 0, 1, 2};
     lay_cycle(L, key_bits, 6, v6, c6);
     return 0;
   }
-  return -1;
+  if (kind >= 3 && kind <= 7 && key_bits != 32) return -1;
+  switch (kind) {
+    case 3:
+      lay_run(L, SRC_O, 32);
+      return 0;
+    case 4:
+      lay_run(L, SRC_D, 8);
+      lay_run(L, SRC_O, 24);
+      return 0;
+    case 5: {
+      int8_t v6[6] = {SRC_O, SRC_O, SRC_O, SRC_D, SRC_D, SRC_D};
+      int8_t c6[6] = {0, 1, 2, 0, 1, 2};
+      lay_cycle(L, 32, 6, v6, c6);
+      int seen[3] = {0, 0, 0};
+      for (int j = 0; j < L->n; ++j)
+        if (L->src[j] == SRC_D && seen[(int)L->comp[j]]++ < 3) L->src[j] = SRC_ZERO;
+      return 0;
+    }
+    case 6:
+      lay_run(L, SRC_O, 12);
+      for (int r = 0; r < 3; ++r) {
+        lay_run(L, SRC_D, 3);
+        lay_run(L, SRC_O, 3);
+      }
+      lay_run(L, SRC_D, 2);
+      return 0;
+    case 7:
+      lay_run(L, SRC_O, 15);
+      for (int r = 0; r < 3; ++r) {
+        lay_run(L, SRC_Q, 2);
+        lay_run(L, SRC_O, 3);
+      }
+      lay_run(L, SRC_Q, 2);
+      return 0;
+    case KIND_CODE20: /* the 20 leading slots of Aila Compact */
+      lay_run(L, SRC_O, 12);
+      lay_run(L, SRC_D, 3);
+      lay_run(L, SRC_O, 3);
+      lay_run(L, SRC_D, 2);
+      return 0;
+    default:
+      return -1;
+  }
 }
 
 static uint32_t quantize(float x, float lo, float inv, int b) {
@@ -92,6 +157,78 @@ static uint32_t quantize(float x, float lo, float inv, int b) {
   return q;
 }
 
+/* Octahedral parametrisation of a direction (Meyer et al. 2010; the layout
+ * of Section 3.1.4): project onto |x| + |y| + |z| = 1; the lower half
+ * (z < 0) folds over the diagonals.  sign(x) is +1 for x >= 0, else -1.
+ * Binary32 in this order. */
+void orc_octahedral(const float* d, float* u_out, float* v_out) {
+  float s = (fabsf(d[0]) + fabsf(d[1])) + fabsf(d[2]);
+  float px = d[0] / s;
+  float py = d[1] / s;
+  if (d[2] < 0.0f) {
+    float sx = px >= 0.0f ? 1.0f : -1.0f;
+    float sy = py >= 0.0f ? 1.0f : -1.0f;
+    float fx = (1.0f - fabsf(py)) * sx;
+    float fy = (1.0f - fabsf(px)) * sy;
+    px = fx;
+    py = fy;
+  }
+  *u_out = px;
+  *v_out = py;
+}
+
+/* ------------------------------------------------------- length table
+ * Two Point Adaptive (Section 3.1.6): a table of 2^20 cells indexed by the
+ * 20-bit Aila Compact code of the ray (origin and direction), holding the
+ * sum of the traced lengths of the rays that fell in the cell and their
+ * count; the estimate is their mean.  Every cell starts with one dummy ray of
+ * length ratio x the largest extent.
+ * Readings: a cell is {uint64 sum; uint32 count; uint32 unused} (16 bytes);
+ * lengths are summed in fixed point, in units of E / 2^24 (E the largest
+ * extent), truncated: fixed(t) = trunc(t * (2^24 / E)) clamped to
+ * [0, 2^40], so the sums do not depend on the order of accumulation; only
+ * hits (prim >= 0) are accumulated; the estimate is
+ * (float)((double)sum * E / ((double)count * 2^24)). */
+typedef struct {
+  uint64_t sum;
+  uint32_t count;
+  uint32_t unused;
+} orc_cell;
+
+#define ORC_CELLS (1u << 20)
+
+static float box_extent(const float* box_lo, const float* box_hi) {
+  float E = box_hi[0] - box_lo[0];
+  for (int k = 1; k < 3; ++k) {
+    float e = box_hi[k] - box_lo[k];
+    if (e > E) E = e;
+  }
+  return E;
+}
+
+void orc_len_init(void* table, float ratio) {
+  orc_cell* c = (orc_cell*)table;
+  uint64_t s0 = (uint64_t)(ratio * 16777216.0f);
+  for (uint32_t i = 0; i < ORC_CELLS; ++i) {
+    c[i].sum = s0;
+    c[i].count = 1;
+    c[i].unused = 0;
+  }
+}
+
+static uint64_t len_fixed(float t, float s24) {
+  float x = t * s24;
+  if (!(x > 0.0f)) return 0;
+  if (x > 1099511627776.0f) return 1099511627776ull;
+  return (uint64_t)x;
+}
+
+static float len_estimate(const orc_cell* c, float E) {
+  double num = (double)c->sum * (double)E;
+  double den = (double)c->count * 16777216.0;
+  return (float)(num / den);
+}
+
 /* Slot layout as (src, comp) per bit, MSB first, for inspection by tests. */
 int orc_key_layout(int32_t kind, int32_t key_bits, int32_t origin_bits, int8_t* src, int8_t* comp) {
   orc_layout L;
@@ -101,18 +238,103 @@ int orc_key_layout(int32_t kind, int32_t key_bits, int32_t origin_bits, int8_t* 
   return 0;
 }
 
+/* Quantised values q[vector][component] of one ray for layout L (bits per
+ * (vector, component) in `bits`); `len` is the termination length used for
+ * the T vector. */
+static void ray_values(const float* r, const float* box_lo, const float* inv, int bits[4][3], float len,
+                       uint32_t q[4][3]) {
+  memset(q, 0, sizeof(uint32_t) * 12);
+  for (int k = 0; k < 3; ++k) {
+    q[SRC_O][k] = quantize(r[k], box_lo[k], inv[k], bits[SRC_O][k]);
+    q[SRC_D][k] = quantize(r[4 + k], -1.0f, 0.5f, bits[SRC_D][k]);
+    float step = len * r[4 + k];
+    float tk = r[k] + step;
+    q[SRC_T][k] = quantize(tk, box_lo[k], inv[k], bits[SRC_T][k]);
+  }
+  float u, v;
+  orc_octahedral(r + 4, &u, &v);
+  q[SRC_Q][0] = quantize(u, -1.0f, 0.5f, bits[SRC_Q][0]);
+  q[SRC_Q][1] = quantize(v, -1.0f, 0.5f, bits[SRC_Q][1]);
+}
+
+static void layout_bits(const orc_layout* L, int bits[4][3]) {
+  memset(bits, 0, sizeof(int) * 12);
+  for (int j = 0; j < L->n; ++j)
+    if (L->src[j] >= 0) bits[(int)L->src[j]][(int)L->comp[j]]++;
+}
+
+/* Assemble a key from the slot list, each component's bits MSB first. */
+static uint64_t assemble(const orc_layout* L, int bits[4][3], uint32_t q[4][3]) {
+  int used[4][3] = {{0}};
+  uint64_t key = 0;
+  for (int j = 0; j < L->n; ++j) {
+    uint64_t bit = 0;
+    int s = L->src[j], c = L->comp[j];
+    if (s >= 0) {
+      int b = bits[s][c];
+      int which = b - 1 - used[s][c];
+      used[s][c]++;
+      bit = (q[s][c] >> which) & 1u;
+    }
+    key |= bit << (L->n - 1 - j);
+  }
+  return key;
+}
+
+/* 20-bit cell code of a ray (the Aila Compact prefix) for the length table. */
+uint32_t orc_cell_code(const float* ray, const float* box_lo, const float* box_hi) {
+  orc_layout L;
+  make_layout(KIND_CODE20, 20, 0, &L);
+  int bits[4][3];
+  layout_bits(&L, bits);
+  float inv[3];
+  for (int k = 0; k < 3; ++k) {
+    float e = box_hi[k] - box_lo[k];
+    inv[k] = e > 0.0f ? 1.0f / e : 0.0f;
+  }
+  uint32_t q[4][3];
+  ray_values(ray, box_lo, inv, bits, 0.0f, q);
+  return (uint32_t)assemble(&L, bits, q);
+}
+
+/* Adds the traced lengths of n rays to the table (hits[i] belongs to
+ * rays[i]). */
+void orc_len_accumulate(void* table, const float* rays, const void* hits, int64_t n, const float* box_lo,
+                        const float* box_hi) {
+  orc_cell* c = (orc_cell*)table;
+  float E = box_extent(box_lo, box_hi);
+  float s24 = 16777216.0f / E;
+  const unsigned char* h = (const unsigned char*)hits;
+  for (int64_t i = 0; i < n; ++i) {
+    float t;
+    int32_t prim;
+    memcpy(&t, h + 16 * i, 4);
+    memcpy(&prim, h + 16 * i + 4, 4);
+    if (prim < 0) continue;
+    uint32_t cell = orc_cell_code(rays + 8 * i, box_lo, box_hi);
+    c[cell].sum += len_fixed(t, s24);
+    c[cell].count += 1;
+  }
+}
+
+/* Length estimate the table gives a ray. */
+float orc_len_lookup(const void* table, const float* ray, const float* box_lo, const float* box_hi) {
+  const orc_cell* c = (const orc_cell*)table;
+  return len_estimate(&c[orc_cell_code(ray, box_lo, box_hi)], box_extent(box_lo, box_hi));
+}
+
 /* Keys for n rays.  keys_out holds n uint64 values (32-bit keys occupy the
- * low half).  Returns 0, or -1 on a bad argument. */
+ * low half).  aux: the length table (kind 8) or the hits of the rays, 16
+ * bytes each (kind 9); unused otherwise.  Returns 0, or -1 on a bad
+ * argument. */
 int orc_keys(const float* rays, int64_t n, int32_t kind, int32_t key_bits, const float* box_lo,
-             const float* box_hi, float ratio, int32_t origin_bits, uint64_t* keys_out) {
+             const float* box_hi, float ratio, int32_t origin_bits, const void* aux, uint64_t* keys_out) {
   if (key_bits != 32 && key_bits != 64) return -1;
   orc_layout L;
   if (make_layout(kind, key_bits, origin_bits, &L) != 0 || L.n != key_bits) return -1;
-
-  /* bits per (vector, component) = number of its slots */
-  int bits[3][3] = {{0}};
-  for (int j = 0; j < L.n; ++j)
-    if (L.src[j] >= 0) bits[(int)L.src[j]][(int)L.comp[j]]++;
+  if ((kind == 8 || kind == 9) && !aux) return -1;
+  int bits[4][3];
+  layout_bits(&L, bits);
 
   float ext[3], inv[3];
   for (int k = 0; k < 3; ++k) {
@@ -126,34 +348,22 @@ int orc_keys(const float* rays, int64_t n, int32_t kind, int32_t key_bits, const
 
   for (int64_t i = 0; i < n; ++i) {
     const float* r = rays + 8 * i;
-    uint32_t q[3][3] = {{0}};
-    for (int k = 0; k < 3; ++k) {
-      q[SRC_O][k] = quantize(r[k], box_lo[k], inv[k], bits[SRC_O][k]);
-      q[SRC_D][k] = quantize(r[4 + k], -1.0f, 0.5f, bits[SRC_D][k]);
+    float tmax = r[7];
+    float len = (tmax < Lfix) ? tmax : Lfix;
+    if (kind == 8) {
+      float est = orc_len_lookup(aux, r, box_lo, box_hi);
+      len = (tmax < est) ? tmax : est;
+    } else if (kind == 9) {
+      const unsigned char* h = (const unsigned char*)aux + 16 * i;
+      float t;
+      int32_t prim;
+      memcpy(&t, h, 4);
+      memcpy(&prim, h + 4, 4);
+      if (prim >= 0) len = t;
     }
-    if (kind == 2) {
-      float tmax = r[7];
-      float len = (tmax < Lfix) ? tmax : Lfix;
-      for (int k = 0; k < 3; ++k) {
-        float step = len * r[4 + k];
-        float tk = r[k] + step;
-        q[SRC_T][k] = quantize(tk, box_lo[k], inv[k], bits[SRC_T][k]);
-      }
-    }
-    int used[3][3] = {{0}};
-    uint64_t key = 0;
-    for (int j = 0; j < L.n; ++j) {
-      uint64_t bit = 0;
-      int s = L.src[j], c = L.comp[j];
-      if (s >= 0) {
-        int b = bits[s][c];
-        int which = b - 1 - used[s][c];
-        used[s][c]++;
-        bit = (q[s][c] >> which) & 1u;
-      }
-      key |= bit << (L.n - 1 - j);
-    }
-    keys_out[i] = key;
+    uint32_t q[4][3];
+    ray_values(r, box_lo, inv, bits, len, q);
+    keys_out[i] = assemble(&L, bits, q);
   }
   return 0;
 }
