@@ -65,31 +65,55 @@ typedef struct rr_hit {
   float u, v;
 } rr_hit;
 
-/* Sort-key methods of Section 3.1. */
+/* Sort-key methods of Section 3.1 and Figure "codes". */
 typedef enum rr_key_kind {
-  RR_KEY_NONE = 0,               /* no reordering (identity order) */
-  RR_KEY_ORIGIN_DIRECTION = 1,   /* Section 3.1.2 (Reis et al.): origin bits above direction bits */
-  RR_KEY_ORIGIN_TERMINATION = 2  /* Section 3.1.5 "Two Point": origin and estimated termination
-                                    point interleaved, fixed-length estimate of Section 3.1.6 */
+  RR_KEY_NONE = 0,                 /* no reordering (identity order) */
+  RR_KEY_ORIGIN_DIRECTION = 1,     /* Section 3.1.2 (Reis et al.): origin bits above direction bits */
+  RR_KEY_ORIGIN_TERMINATION = 2,   /* Section 3.1.5 "Two Point": origin and estimated termination
+                                      point interleaved, fixed-length estimate of Section 3.1.6 */
+  RR_KEY_ORIGIN = 3,               /* Section 3.1.1: origin only */
+  RR_KEY_DIRECTION_ORIGIN = 4,     /* Section 3.1.3 (Costa et al.): direction bits above origin bits */
+  RR_KEY_AILA = 5,                 /* Section 3.1.4 (Aila and Karras): origin and direction
+                                      interleaved, three leading zero bits per direction component */
+  RR_KEY_AILA_COMPACT = 6,         /* Section 3.1.4: the compacted variant, no zero bits */
+  RR_KEY_OCTAHEDRON = 7,           /* Section 3.1.4: origin with an octahedral direction */
+  RR_KEY_TWO_POINT_ADAPTIVE = 8,   /* Section 3.1.6: Two Point, length from a length table */
+  RR_KEY_TWO_POINT_REAL = 9        /* Section 3.1.6 reference: Two Point at the traced termination */
 } rr_key_kind;
 
 /* Key parameters.
  *  kind        one of rr_key_kind.
- *  key_bits    32 or 64.
+ *  key_bits    32 or 64; kinds 3-7 exist with 32 bits only (the layouts of
+ *              Figure "codes"); RR_ERR_UNSUPPORTED otherwise.
  *  box_lo/hi   quantisation box for origins and termination points, normally
  *              the scene bounds (rr_scene_bounds).  A flat axis quantises to 0.
- *  term_ratio  Two Point only: estimated ray length = term_ratio x the
- *              largest box extent, capped at the ray's tmax (Section 3.1.6
- *              uses 0.25).
+ *  term_ratio  Two Point kinds: the fixed estimated ray length is term_ratio
+ *              x the largest box extent E, capped at the ray's tmax (Section
+ *              3.1.6 uses 0.25); it is also the length of the dummy ray each
+ *              length-table cell starts with.
  *  origin_bits origin-direction only: number of origin bits; 0 selects 22
  *              for 32-bit keys (Figure "codes", Reis row) and 44 for 64-bit.
- * Bit layout, most significant first: origin-direction = origin_bits slots
- * cycling (o.x, o.y, o.z) then key_bits - origin_bits slots cycling
- * (d.x, d.y, d.z); Two Point = key_bits slots cycling
- * (o.x, o.y, o.z, t.x, t.y, t.z).  A component owning b slots is quantised
- * as q = min(trunc(clamp((x - lo) / (hi - lo), 0, 1) * 2^b), 2^b - 1)
- * (directions use lo = -1, hi = 1), its most significant bit in its first
- * slot. */
+ *  aux         RR_KEY_TWO_POINT_ADAPTIVE: the device length table
+ *              (rr_length_cell[RR_LENGTH_CELLS], see rr_length_table_init);
+ *              RR_KEY_TWO_POINT_REAL: device rr_hit[n], hits[i] the traced hit
+ *              of rays[i]; NULL (ignored) for the other kinds.
+ * Bit layouts, most significant first; a run cycles the components x, y, z
+ * (u, v for the octahedral direction):
+ *   origin-direction  origin_bits slots of o, then key_bits - origin_bits of d
+ *   Two Point (2/8/9) key_bits slots cycling (o.x, o.y, o.z, t.x, t.y, t.z)
+ *   origin            o32
+ *   direction-origin  d8 o24
+ *   Aila              (o3 d3) x 5, o2, the first three slots of each direction
+ *                     component are zero bits
+ *   Aila Compact      o12 d3 o3 d3 o3 d3 o3 d2
+ *   octahedron        o15 q2 o3 q2 o3 q2 o3 q2, q the octahedral (u, v)
+ * A component owning b slots is quantised as
+ * q = min(trunc(clamp((x - lo) / (hi - lo), 0, 1) * 2^b), 2^b - 1)
+ * (directions and octahedral coordinates use lo = -1, hi = 1), its most
+ * significant bit in its first slot.  The octahedral coordinates of d are
+ * (x, y) of d / (|d.x| + |d.y| + |d.z|), folded for d.z < 0 to
+ * ((1 - |y|) sgn x, (1 - |x|) sgn y) with sgn(0) = +1.  Two Point Real uses
+ * the traced length for hits and the fixed estimate for misses. */
 typedef struct rr_key_params {
   int32_t kind;
   uint32_t key_bits;
@@ -97,7 +121,22 @@ typedef struct rr_key_params {
   float box_hi[3];
   float term_ratio;
   uint32_t origin_bits;
+  const void* aux;
 } rr_key_params;
+
+/* Two Point Adaptive length table (Section 3.1.6): RR_LENGTH_CELLS cells
+ * indexed by the 20-bit Aila Compact code of a ray (the 20 leading slots of
+ * that layout: origin 5/5/5 bits, direction 2/2/1 bits), each holding the sum
+ * of the lengths of the rays traced from it and their count.  Lengths are
+ * held in units of E / 2^24 (E the largest box extent) and truncated, so
+ * sums do not depend on the order rays are added in; the estimate is
+ * (float)(sum * E / (count * 2^24)) in double precision. */
+#define RR_LENGTH_CELLS (1u << 20)
+typedef struct rr_length_cell {
+  uint64_t sum;
+  uint32_t count;
+  uint32_t unused;
+} rr_length_cell;
 
 typedef struct rr_scene_s* rr_scene;
 
@@ -141,6 +180,21 @@ rr_status rr_keys_workspace_size(int64_t n, size_t* bytes);
 rr_status rr_compute_keys(const rr_ray* rays, int64_t n, const uint8_t* alive, const rr_key_params* p,
                           void* keys_out, uint32_t* idx_out, uint32_t* count_out, void* workspace, size_t ws_bytes,
                           void* stream);
+
+/* Length table of Two Point Adaptive (Section 3.1.6).
+ * rr_length_table_init writes every cell of the device table (RR_LENGTH_CELLS
+ * x 16 bytes, caller-owned) as one dummy ray of length p->term_ratio x E:
+ * {trunc(term_ratio * 2^24), 1}.  rr_length_table_accumulate adds the traced
+ * length of every hit (prim >= 0) among hits[0, n) to the cell of the ray
+ * it belongs to, rays[idx ? idx[i] : i] for hits[i]; with count_dev (device
+ * uint32) only the first min(*count_dev, n) hits.  Adding is atomic and
+ * exact, so concurrent calls on one table commute.  p gives the
+ * quantisation box (its kind is not used).  rr_reorder_and_trace with
+ * RR_KEY_TWO_POINT_ADAPTIVE calls it for the rays it traced. */
+rr_status rr_length_table_init(rr_length_cell* table, const rr_key_params* p, void* stream);
+rr_status rr_length_table_accumulate(rr_length_cell* table, const rr_ray* rays, const uint32_t* idx,
+                                     const rr_hit* hits, int64_t n, const uint32_t* count_dev,
+                                     const rr_key_params* p, void* stream);
 
 /* ------------------------------------------------------------------- sort
  * Section 3.2: stable ascending LSD radix sort of (key, index) pairs, in
@@ -211,7 +265,9 @@ rr_status rr_trace_profile(rr_scene s, const rr_ray* rays, int64_t n, rr_hit* hi
  *            RR_KEY_NONE; compacted live indices when alive is given).
  *  count_out optional device uint32: the number of traced rays.
  *  workspace device scratch of at least rr_reorder_workspace_size bytes.
- * RR_KEY_NONE traces the (compacted) rays in their original order. */
+ * RR_KEY_NONE traces the (compacted) rays in their original order.
+ * RR_KEY_TWO_POINT_ADAPTIVE computes its keys from the table p->aux and,
+ * after the trace, adds the traced lengths to that table. */
 #define RR_HITS_ORIGINAL_ORDER 1u
 /* Trace through the sorted index instead of gathering the rays first
  * (Section 4.4.1, indirect ray access). */

@@ -22,7 +22,10 @@ extern "C" {
  * ray order with RR_HITS_ORIGINAL_ORDER, else in the segment's key order.
  * perm (device, nullable, n entries) receives the segment-local sorted ray
  * indices.  Per segment the results equal those of rr_reorder_and_trace on
- * that wavefront alone, bit for bit. */
+ * that wavefront alone, bit for bit.  Every key kind may be used; a
+ * RR_KEY_TWO_POINT_ADAPTIVE segment reads its length table (key.aux) but the
+ * batch does not add its traced lengths to it (rr_length_table_accumulate
+ * does), so segments sharing a table see the same estimates. */
 typedef struct rr_segment {
   const rr_ray* rays;
   rr_hit* hits;

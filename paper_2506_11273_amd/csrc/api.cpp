@@ -158,6 +158,7 @@ rr_status rr_compute_keys(const rr_ray* rays, int64_t n, const uint8_t* alive, c
   KeyPlan plan;
   rr_status st = make_key_plan(p, &plan);
   if (st != RR_OK) return st;
+  if (plan.aux && (!is_device_ptr(plan.aux) || !aligned(plan.aux, 16))) return RR_ERR_INVALID_ARGUMENT;
   if (alive && !count_out) return RR_ERR_INVALID_ARGUMENT;
   if (count_out && !is_device_ptr(count_out)) return RR_ERR_INVALID_ARGUMENT;
   if (n == 0) return count_out ? launch_set_u32(count_out, 0u, S(stream)) : RR_OK;
@@ -170,6 +171,40 @@ rr_status rr_compute_keys(const rr_ray* rays, int64_t n, const uint8_t* alive, c
     if (ws_bytes < keys_scratch_bytes(n)) return RR_ERR_WORKSPACE_TOO_SMALL;
   }
   return launch_keys(rays, n, alive, plan, keys_out, idx_out, count_out, workspace, S(stream));
+}
+
+// ----------------------------------------------------------- length table
+
+rr_status rr_length_table_init(rr_length_cell* table, const rr_key_params* p, void* stream) {
+  if (!table || !p) return RR_ERR_INVALID_ARGUMENT;
+  if (!is_device_ptr(table) || !aligned(table, 16)) return RR_ERR_INVALID_ARGUMENT;
+  if (!(p->term_ratio >= 0.0f)) return RR_ERR_INVALID_ARGUMENT;
+  rr_key_params q = *p;
+  q.kind = RR_KEY_ORIGIN_TERMINATION;
+  q.key_bits = 32;
+  KeyPlan plan;
+  rr_status st = make_key_plan(&q, &plan);
+  if (st != RR_OK) return st;
+  return launch_length_init(table, plan, p->term_ratio, S(stream));
+}
+
+rr_status rr_length_table_accumulate(rr_length_cell* table, const rr_ray* rays, const uint32_t* idx,
+                                     const rr_hit* hits, int64_t n, const uint32_t* count_dev,
+                                     const rr_key_params* p, void* stream) {
+  if (!table || !p || !valid_n(n)) return RR_ERR_INVALID_ARGUMENT;
+  if (n == 0) return RR_OK;
+  if (!is_device_ptr(table) || !aligned(table, 16) || !is_device_ptr(rays) || !aligned(rays, 16) ||
+      !is_device_ptr(hits) || !aligned(hits, 16))
+    return RR_ERR_INVALID_ARGUMENT;
+  if ((idx && (!is_device_ptr(idx) || !aligned(idx, 4))) || (count_dev && !is_device_ptr(count_dev)))
+    return RR_ERR_INVALID_ARGUMENT;
+  rr_key_params q = *p;
+  q.kind = RR_KEY_ORIGIN_TERMINATION;
+  q.key_bits = 32;
+  KeyPlan plan;
+  rr_status st = make_key_plan(&q, &plan);
+  if (st != RR_OK) return st;
+  return launch_length_accumulate(table, rays, idx, hits, n, count_dev, plan, S(stream));
 }
 
 // ------------------------------------------------------------------- sort
@@ -286,6 +321,7 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
   if (sorted) {
     rr_status st = make_key_plan(p, &plan);
     if (st != RR_OK) return st;
+    if (plan.aux && (!is_device_ptr(plan.aux) || !aligned(plan.aux, 16))) return RR_ERR_INVALID_ARGUMENT;
   }
   hipStream_t st = S(stream);
   if (count_out && !is_device_ptr(count_out)) return RR_ERR_INVALID_ARGUMENT;
@@ -331,6 +367,11 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
   } else {
     if ((r = launch_gather(rays, idx, n, cnt, srays, st)) != RR_OK) return r;
     if ((r = launch_trace(s->d, srays, nullptr, n, cnt, tout, st)) != RR_OK) return r;
+  }
+  if (plan.kind == RR_KEY_TWO_POINT_ADAPTIVE) {
+    // Section 3.1.6: the traced lengths update the table after each trace
+    rr_length_cell* table = const_cast<rr_length_cell*>(reinterpret_cast<const rr_length_cell*>(plan.aux));
+    if ((r = launch_length_accumulate(table, rays, idx, tout, n, cnt, plan, st)) != RR_OK) return r;
   }
   if (orig) {
     if (alive && (r = launch_fill_miss(hits, n, st)) != RR_OK) return r;

@@ -70,8 +70,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_keys(const BatchHdr* __re
     if (S.plan.kind != 0) {
       const float4 a = S.rays[2 * (size_t)r];
       const float4 b = S.rays[2 * (size_t)r + 1];
-      key = S.plan.kind == RR_KEY_ORIGIN_DIRECTION ? ray_key<RR_KEY_ORIGIN_DIRECTION>(a, b, S.plan)
-                                                   : ray_key<RR_KEY_ORIGIN_TERMINATION>(a, b, S.plan);
+      key = ray_key_any(a, b, S.plan, r);
       key <<= S.shift;
     }
     keys[p] = (K)key;
@@ -272,6 +271,8 @@ rr_status stage(rr_batch b, const rr_segment* segs, int32_t nseg, uint32_t flags
     if (g.key.kind != RR_KEY_NONE) {
       rr_status r = make_key_plan(&g.key, &B.plan);
       if (r != RR_OK) return r;
+      if (B.plan.aux && (!is_dev(B.plan.aux) || (reinterpret_cast<uintptr_t>(B.plan.aux) & 15)))
+        return RR_ERR_INVALID_ARGUMENT;
       B.shift = (kb == 64 && g.key.key_bits == 32) ? 32u : 0u;
     }
     std::memcpy(&bs[s], &B, sizeof B);

@@ -30,6 +30,16 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // component c (0-2 origin, 3-5 direction or termination point) owns
 // bits[c] key slots, spaced `stride` apart, its least significant bit
 // landing at key bit shift[c].
+// One field of a general key layout: cnt bits of component comp, taken
+// below its src_shift lowest bits, placed at key bits dst_shift,
+// dst_shift + stride, ... (lowest first).
+struct KeyField {
+  uint8_t comp, cnt, stride, src_shift, dst_shift, pad[3];
+};
+
+constexpr int kMaxKeyFields = 12;
+constexpr uint32_t kLengthCells = 1u << 20;
+
 struct KeyPlan {
   float lo[3];
   float inv[3];
@@ -37,8 +47,16 @@ struct KeyPlan {
   float scale[6];       // 2^bits as float
   uint32_t qmax[6];     // 2^bits - 1
   int32_t shift[6];
-  int32_t kind;         // 1 origin-direction, 2 Two Point
+  int32_t kind;         // rr_key_kind
   int32_t key64;        // 0: 32-bit keys, 1: 64-bit keys
+  // the figure's other layouts: components 0-2 origin, 3-5 direction (or
+  // 3-4 octahedral u, v), placed field by field
+  int32_t nfields;
+  KeyField field[kMaxKeyFields];
+  // Two Point Adaptive: the length table; Two Point Real: the rays' hits
+  const void* aux;
+  float E;              // largest box extent
+  float s24;            // 2^24 / E: length-table units per unit length
 };
 
 rr_status make_key_plan(const rr_key_params* p, KeyPlan* out);
@@ -49,6 +67,12 @@ rr_status launch_keys(const rr_ray* rays, int64_t n, const uint8_t* alive, const
 rr_status launch_compact_only(int64_t n, const uint8_t* alive, uint32_t* idx, uint32_t* count_out,
                               void* block_scratch, hipStream_t st);
 size_t keys_scratch_bytes(int64_t n);
+// Two Point Adaptive length table (rr_length_cell[kLengthCells]).
+rr_status launch_length_init(rr_length_cell* table, const KeyPlan& plan, float ratio, hipStream_t st);
+// Adds hits[i] (i < min(*count_dev, n_max)) of rays[idx ? idx[i] : i].
+rr_status launch_length_accumulate(rr_length_cell* table, const rr_ray* rays, const uint32_t* idx,
+                                   const rr_hit* hits, int64_t n_max, const uint32_t* count_dev,
+                                   const KeyPlan& plan, hipStream_t st);
 
 // --------------------------------------------------------------- sort
 size_t sort_workspace_bytes(int64_t n_max, uint32_t key_bits, uint32_t digit_bits, uint32_t kpt);

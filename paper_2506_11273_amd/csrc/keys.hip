@@ -1,5 +1,6 @@
 // Sort-key computation (Section 3.1, Figure "codes") with optional stable
-// compaction of live rays.
+// compaction of live rays, and the length table of Two Point Adaptive
+// (Section 3.1.6).
 //
 // Each key is the Morton-style interleave of quantised ray coordinates: an
 // origin-direction key (Section 3.1.2) puts the origin bits above the
@@ -17,10 +18,78 @@
 
 namespace rr {
 
+namespace {
+
+// The figure's other layouts as runs of slots, most significant first.  A
+// run cycles its vector's components; vector 0 origin, 1 direction, 2 zero
+// slots, 3 octahedral (u, v).
+struct Run {
+  int vec, n;
+};
+
+// Places each component's slots and splits them into fields of equally
+// spaced slots.
+rr_status general_plan(int kind, KeyPlan* P) {
+  static const Run kOrigin[] = {{0, 32}};
+  static const Run kCosta[] = {{1, 8}, {0, 24}};
+  static const Run kAila[] = {{0, 3}, {2, 3}, {0, 3}, {2, 3}, {0, 3}, {2, 3}, {0, 3}, {1, 3}, {0, 3}, {1, 3}, {0, 2}};
+  static const Run kAilaCompact[] = {{0, 12}, {1, 3}, {0, 3}, {1, 3}, {0, 3}, {1, 3}, {0, 3}, {1, 2}};
+  static const Run kOctahedron[] = {{0, 15}, {3, 2}, {0, 3}, {3, 2}, {0, 3}, {3, 2}, {0, 3}, {3, 2}};
+  const Run* runs = nullptr;
+  int nruns = 0;
+  switch (kind) {
+    case RR_KEY_ORIGIN: runs = kOrigin; nruns = 1; break;
+    case RR_KEY_DIRECTION_ORIGIN: runs = kCosta; nruns = 2; break;
+    case RR_KEY_AILA: runs = kAila; nruns = 11; break;
+    case RR_KEY_AILA_COMPACT: runs = kAilaCompact; nruns = 8; break;
+    case RR_KEY_OCTAHEDRON: runs = kOctahedron; nruns = 8; break;
+    default: return RR_ERR_INVALID_ARGUMENT;
+  }
+  int pos[6][32];  // key bit of each component's slots, its MSB first
+  int npos[6] = {0, 0, 0, 0, 0, 0};
+  int slot = 31;
+  for (int r = 0; r < nruns; ++r) {
+    const int ncomp = runs[r].vec == 3 ? 2 : 3;
+    for (int i = 0; i < runs[r].n; ++i, --slot) {
+      if (runs[r].vec == 2) continue;
+      const int c = (runs[r].vec == 0 ? 0 : 3) + i % ncomp;
+      pos[c][npos[c]++] = slot;
+    }
+  }
+  if (slot != -1) return RR_ERR_INVALID_ARGUMENT;
+  P->nfields = 0;
+  for (int c = 0; c < 6; ++c) {
+    const int b = npos[c];
+    P->scale[c] = b ? (float)(1u << b) : 1.0f;
+    P->qmax[c] = b ? (1u << b) - 1u : 0u;
+    P->shift[c] = 0;
+    for (int k = 0; k < b;) {
+      const int stride = k + 1 < b ? pos[c][k] - pos[c][k + 1] : 1;
+      int e = k + 1;
+      while (e < b && pos[c][e - 1] - pos[c][e] == stride) ++e;
+      if (P->nfields == kMaxKeyFields) return RR_ERR_INVALID_ARGUMENT;
+      KeyField& F = P->field[P->nfields++];
+      F.comp = (uint8_t)c;
+      F.cnt = (uint8_t)(e - k);
+      F.stride = (uint8_t)stride;
+      F.src_shift = (uint8_t)(b - e);
+      F.dst_shift = (uint8_t)pos[c][e - 1];
+      k = e;
+    }
+  }
+  return RR_OK;
+}
+
+}  // namespace
+
 rr_status make_key_plan(const rr_key_params* p, KeyPlan* out) {
   if (!p || !out) return RR_ERR_INVALID_ARGUMENT;
   if (p->key_bits != 32 && p->key_bits != 64) return RR_ERR_INVALID_ARGUMENT;
-  if (p->kind != RR_KEY_ORIGIN_DIRECTION && p->kind != RR_KEY_ORIGIN_TERMINATION) return RR_ERR_INVALID_ARGUMENT;
+  if (p->kind < RR_KEY_ORIGIN_DIRECTION || p->kind > RR_KEY_TWO_POINT_REAL) return RR_ERR_INVALID_ARGUMENT;
+  const bool general = p->kind >= RR_KEY_ORIGIN && p->kind <= RR_KEY_OCTAHEDRON;
+  if (general && p->key_bits != 32) return RR_ERR_UNSUPPORTED;
+  const bool needs_aux = p->kind == RR_KEY_TWO_POINT_ADAPTIVE || p->kind == RR_KEY_TWO_POINT_REAL;
+  if (needs_aux && !p->aux) return RR_ERR_INVALID_ARGUMENT;
   KeyPlan P{};
   const int K = (int)p->key_bits;
   float ext[3];
@@ -33,8 +102,11 @@ rr_status make_key_plan(const rr_key_params* p, KeyPlan* out) {
   if (ext[1] > E) E = ext[1];
   if (ext[2] > E) E = ext[2];
   P.len = p->term_ratio * E;
+  P.E = E;
+  P.s24 = 16777216.0f / E;
   P.kind = p->kind;
   P.key64 = K == 64;
+  P.aux = needs_aux ? p->aux : nullptr;
 
   // A field of S slots starting at key bit `base`, cycling over `cyc`
   // components: component j owns ceil((S - j) / cyc) slots; its slot m
@@ -60,6 +132,9 @@ rr_status make_key_plan(const rr_key_params* p, KeyPlan* out) {
     if (ob > K) return RR_ERR_INVALID_ARGUMENT;
     place(0, 3, 3, ob, K - ob);
     place(3, 3, 3, K - ob, 0);
+  } else if (general) {
+    rr_status st = general_plan(p->kind, &P);
+    if (st != RR_OK) return st;
   } else {
     // the six components cycle together over the whole key
     int S = K;
@@ -92,7 +167,7 @@ __global__ __launch_bounds__(kKeyBlock) void k_keys_dense(const float4* __restri
   if (i >= n) return;
   const float4 a = rays[2 * (size_t)i];
   const float4 b = rays[2 * (size_t)i + 1];
-  keys[i] = (K)ray_key<KIND>(a, b, P);
+  keys[i] = (K)ray_key<KIND>(a, b, P, i);
   idx[i] = i;
 }
 
@@ -175,7 +250,7 @@ __global__ __launch_bounds__(kKeyBlock) void k_keys_compact(const float4* __rest
       if constexpr (WITH_KEYS) {
         const float4 a = rays[2 * (size_t)i];
         const float4 b = rays[2 * (size_t)i + 1];
-        keys[pos] = (K)ray_key<KIND>(a, b, P);
+        keys[pos] = (K)ray_key<KIND>(a, b, P, i);
       }
       idx[pos] = i;
     }
@@ -213,12 +288,67 @@ size_t keys_scratch_bytes(int64_t n) {
 rr_status launch_keys(const rr_ray* rays, int64_t n, const uint8_t* alive, const KeyPlan& P, void* keys,
                       uint32_t* idx, uint32_t* count_out, void* block_scratch, hipStream_t st) {
   uint32_t* bs = reinterpret_cast<uint32_t*>(block_scratch);
-  if (P.kind == RR_KEY_ORIGIN_DIRECTION) {
-    if (P.key64) return keys_impl<1, uint64_t>(rays, n, alive, P, (uint64_t*)keys, idx, count_out, bs, st);
-    return keys_impl<1, uint32_t>(rays, n, alive, P, (uint32_t*)keys, idx, count_out, bs, st);
+  switch (key_family(P.kind)) {
+    case 1:
+      if (P.key64) return keys_impl<1, uint64_t>(rays, n, alive, P, (uint64_t*)keys, idx, count_out, bs, st);
+      return keys_impl<1, uint32_t>(rays, n, alive, P, (uint32_t*)keys, idx, count_out, bs, st);
+    case 2:
+      if (P.key64) return keys_impl<2, uint64_t>(rays, n, alive, P, (uint64_t*)keys, idx, count_out, bs, st);
+      return keys_impl<2, uint32_t>(rays, n, alive, P, (uint32_t*)keys, idx, count_out, bs, st);
+    default:
+      return keys_impl<3, uint32_t>(rays, n, alive, P, (uint32_t*)keys, idx, count_out, bs, st);
   }
-  if (P.key64) return keys_impl<2, uint64_t>(rays, n, alive, P, (uint64_t*)keys, idx, count_out, bs, st);
-  return keys_impl<2, uint32_t>(rays, n, alive, P, (uint32_t*)keys, idx, count_out, bs, st);
+}
+
+namespace {
+
+__global__ __launch_bounds__(kKeyBlock) void k_length_init(rr_length_cell* __restrict__ table, uint64_t sum0) {
+  const uint32_t i = blockIdx.x * kKeyBlock + threadIdx.x;
+  if (i < kLengthCells) table[i] = rr_length_cell{sum0, 1u, 0u};
+}
+
+// Adds the traced length of each hit to its ray's cell: fixed point in
+// units of E / 2^24, truncated, clamped to [0, 2^40].
+__global__ __launch_bounds__(kKeyBlock) void k_length_accumulate(rr_length_cell* __restrict__ table,
+                                                                 const float4* __restrict__ rays,
+                                                                 const uint32_t* __restrict__ idx,
+                                                                 const float4* __restrict__ hits, uint32_t n_max,
+                                                                 const uint32_t* count_dev, KeyPlan P) {
+  const uint32_t n = count_dev ? min(*count_dev, n_max) : n_max;
+  const uint32_t i = blockIdx.x * kKeyBlock + threadIdx.x;
+  if (i >= n) return;
+  const float4 h = hits[i];
+  if (__float_as_int(h.y) < 0) return;
+  const uint32_t r = idx ? idx[i] : i;
+  const float4 a = rays[2 * (size_t)r];
+  const float4 b = rays[2 * (size_t)r + 1];
+  const float x = h.x * P.s24;
+  const uint64_t q = !(x > 0.0f) ? 0ull : (x > 1099511627776.0f ? 1099511627776ull : (uint64_t)x);
+  rr_length_cell* c = &table[cell_code(a, b, P)];
+  atomicAdd(reinterpret_cast<unsigned long long*>(&c->sum), (unsigned long long)q);
+  atomicAdd(&c->count, 1u);
+}
+
+}  // namespace
+
+rr_status launch_length_init(rr_length_cell* table, const KeyPlan& P, float ratio, hipStream_t st) {
+  (void)P;
+  const uint64_t sum0 = (uint64_t)(ratio * 16777216.0f);
+  hipLaunchKernelGGL(k_length_init, dim3(kLengthCells / kKeyBlock), dim3(kKeyBlock), 0, st, table, sum0);
+  RR_LAUNCH_CHECK();
+  return RR_OK;
+}
+
+rr_status launch_length_accumulate(rr_length_cell* table, const rr_ray* rays, const uint32_t* idx,
+                                   const rr_hit* hits, int64_t n_max, const uint32_t* count_dev, const KeyPlan& P,
+                                   hipStream_t st) {
+  if (n_max == 0) return RR_OK;
+  const uint32_t blocks = (uint32_t)((n_max + kKeyBlock - 1) / kKeyBlock);
+  hipLaunchKernelGGL(k_length_accumulate, dim3(blocks), dim3(kKeyBlock), 0, st, table,
+                     reinterpret_cast<const float4*>(rays), idx, reinterpret_cast<const float4*>(hits),
+                     (uint32_t)n_max, count_dev, P);
+  RR_LAUNCH_CHECK();
+  return RR_OK;
 }
 
 rr_status launch_compact_only(int64_t n, const uint8_t* alive, uint32_t* idx, uint32_t* count_out,

@@ -261,6 +261,7 @@ rr_status rr_server_submit(rr_server sv, const rr_ray* rays, int64_t n, const rr
     rr::KeyPlan p;
     const rr_status st = rr::make_key_plan(key, &p);
     if (st != RR_OK) return st;
+    if (p.aux && !device_ptr(p.aux, 16)) return RR_ERR_INVALID_ARGUMENT;
   }
   // a bad request is refused here so that it never fails its batch-mates
   if (n > 0 && (!device_ptr(rays, 16) || !device_ptr(hits, 16))) return RR_ERR_INVALID_ARGUMENT;

@@ -35,6 +35,14 @@ RR_ERR_BUDGET = -6
 RR_KEY_NONE = 0
 RR_KEY_ORIGIN_DIRECTION = 1
 RR_KEY_ORIGIN_TERMINATION = 2
+RR_KEY_ORIGIN = 3
+RR_KEY_DIRECTION_ORIGIN = 4
+RR_KEY_AILA = 5
+RR_KEY_AILA_COMPACT = 6
+RR_KEY_OCTAHEDRON = 7
+RR_KEY_TWO_POINT_ADAPTIVE = 8
+RR_KEY_TWO_POINT_REAL = 9
+RR_LENGTH_CELLS = 1 << 20
 
 RR_HITS_ORIGINAL_ORDER = 1
 RR_INDIRECT = 2
@@ -43,7 +51,7 @@ RR_INDIRECT = 2
 EXPORTS = (
     "rr_status_string", "rr_device_count",
     "rr_scene_create", "rr_scene_create_ex", "rr_scene_bounds", "rr_scene_info", "rr_scene_destroy",
-    "rr_keys_workspace_size", "rr_compute_keys",
+    "rr_keys_workspace_size", "rr_compute_keys", "rr_length_table_init", "rr_length_table_accumulate",
     "rr_sort_workspace_size", "rr_sort", "rr_sort_ex",
     "rr_gather", "rr_scatter_hits", "rr_trace", "rr_trace_ex", "rr_trace_profile",
     "rr_reorder_workspace_size", "rr_reorder_and_trace",
@@ -60,7 +68,7 @@ class RRError(RuntimeError):
 class KeyParams(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("key_bits", ctypes.c_uint32),
                 ("box_lo", ctypes.c_float * 3), ("box_hi", ctypes.c_float * 3),
-                ("term_ratio", ctypes.c_float), ("origin_bits", ctypes.c_uint32)]
+                ("term_ratio", ctypes.c_float), ("origin_bits", ctypes.c_uint32), ("aux", ctypes.c_void_p)]
 
 
 _lib = None
@@ -88,6 +96,8 @@ def load():
         "rr_scene_destroy": ([vp], st),
         "rr_keys_workspace_size": ([i64, P(sz)], st),
         "rr_compute_keys": ([vp, i64, vp, P(KeyParams), vp, vp, vp, vp, sz, vp], st),
+        "rr_length_table_init": ([vp, P(KeyParams), vp], st),
+        "rr_length_table_accumulate": ([vp, vp, vp, vp, i64, vp, P(KeyParams), vp], st),
         "rr_sort_workspace_size": ([i64, u32, P(sz)], st),
         "rr_sort": ([vp, vp, i64, vp, u32, vp, sz, vp], st),
         "rr_sort_ex": ([vp, vp, i64, vp, u32, u32, u32, vp, sz, vp], st),
@@ -158,7 +168,10 @@ def _stream(stream) -> Optional[int]:
 
 
 def key_params(kind: int, key_bits: int, box_lo, box_hi, term_ratio: float = 0.25,
-               origin_bits: int = 0) -> KeyParams:
+               origin_bits: int = 0, aux=None) -> KeyParams:
+    """aux: the length table (a LengthTable or its device tensor) for
+    RR_KEY_TWO_POINT_ADAPTIVE, the rays' hits (N, 4) float32 device tensor
+    for RR_KEY_TWO_POINT_REAL."""
     p = KeyParams()
     p.kind = int(kind)
     p.key_bits = int(key_bits)
@@ -167,7 +180,41 @@ def key_params(kind: int, key_bits: int, box_lo, box_hi, term_ratio: float = 0.2
         p.box_hi[k] = float(box_hi[k])
     p.term_ratio = float(np.float32(term_ratio))
     p.origin_bits = int(origin_bits)
+    if isinstance(aux, LengthTable):
+        aux = aux.cells
+    p.aux = int(aux.data_ptr()) if aux is not None else None
+    # the tensor must outlive every call that uses these parameters
+    p._aux_ref = aux
     return p
+
+
+class LengthTable:
+    """Two Point Adaptive length table on the device (RR_LENGTH_CELLS cells
+    of 16 bytes), initialised to one dummy ray of term_ratio x the largest
+    extent of params' box per cell."""
+
+    def __init__(self, params: KeyParams, device=None, stream=None):
+        torch = _torch()
+        self.cells = torch.empty((RR_LENGTH_CELLS, 4), dtype=torch.int32, device=device or "cuda")
+        self.params = params
+        _check(load().rr_length_table_init(self.cells.data_ptr(), ctypes.byref(params), _stream(stream)),
+               "rr_length_table_init")
+
+    def accumulate(self, rays, hits, idx=None, count=None, stream=None):
+        torch = _torch()
+        n = int(hits.shape[0])
+        _check(load().rr_length_table_accumulate(self.cells.data_ptr(), _ptr(rays, "rays", torch.float32),
+                                                 _ptr(idx, "idx", torch.int32, False),
+                                                 _ptr(hits, "hits", torch.float32), n,
+                                                 _ptr(count, "count", torch.int32, False),
+                                                 ctypes.byref(self.params), _stream(stream)),
+               "rr_length_table_accumulate")
+
+    def numpy(self):
+        """Cells as a structured array {sum uint64, count uint32, unused uint32}."""
+        import numpy as _np
+        raw = self.cells.cpu().numpy().view(_np.uint8).reshape(-1)
+        return raw.view(_np.dtype([("sum", _np.uint64), ("count", _np.uint32), ("unused", _np.uint32)]))
 
 
 def _n_rows(rays) -> int:
