@@ -14,6 +14,8 @@ Reordering Techniques for Faster GPU Ray Tracing", I3D 2020) directly:
                      (length table) or real (traced) termination point.
 * LengthTable     -- Section 3.1.6: the 2^20-cell table of mean traced
                      lengths keyed by the 20-bit Aila Compact code.
+* coherence_m64   -- Section 4.3: the capsule surface-area coherence measure
+                     of groups of 64 consecutive rays and its mean.
 * sort_pairs      -- Section 3.2: key/index pairs sorted by key; the
                      stable order is the lexicographic order of (key, index).
 * gather          -- Section 3.2: "an additional pass" moving the ray data.
@@ -71,6 +73,7 @@ def _get():
         L.orc_len_init.argtypes = [vp, f32]; L.orc_len_init.restype = None
         L.orc_len_accumulate.argtypes = [vp, vp, vp, i64, vp, vp]; L.orc_len_accumulate.restype = None
         L.orc_len_lookup.argtypes = [vp, vp, vp, vp]; L.orc_len_lookup.restype = f32
+        L.orc_cps.argtypes = [vp, vp, i64, vp, vp, vp, vp]; L.orc_cps.restype = None
         L.orc_key_layout.argtypes = [i32, i32, i32, vp, vp]; L.orc_key_layout.restype = ctypes.c_int
         L.orc_mt.argtypes = [vp, vp, vp, vp, vp, vp]; L.orc_mt.restype = ctypes.c_int
         L.orc_brute_force.argtypes = [vp, i64, vp, i64, vp, i32]; L.orc_brute_force.restype = None
@@ -173,6 +176,20 @@ class LengthTable:
         L = _get()
         return np.array([L.orc_len_lookup(_p(self.cells), _p(r[i]), _p(self.lo), _p(self.hi))
                          for i in range(r.shape[0])], np.float32)
+
+
+def coherence_m64(rays, hits, box_lo, box_hi):
+    """(per-group measures, mean) of M^64_CPS over consecutive groups of 64."""
+    r = _c(rays, np.float32).reshape(-1, 8)
+    h = np.ascontiguousarray(hits, dtype=HIT_DTYPE)
+    if h.shape[0] != r.shape[0]:
+        raise ValueError("one hit per ray")
+    lo = _c(box_lo, np.float32)
+    hi = _c(box_hi, np.float32)
+    g = np.zeros((r.shape[0] + 63) // 64, np.float64)
+    m = ctypes.c_double()
+    _get().orc_cps(_p(r), _p(h), r.shape[0], _p(lo), _p(hi), _p(g), ctypes.byref(m))
+    return g, m.value
 
 
 def scene_box(tris):

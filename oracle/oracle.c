@@ -705,3 +705,88 @@ int64_t orc_compact(const uint8_t* alive, int64_t n, uint32_t* idx_out) {
     if (alive[i]) idx_out[m++] = (uint32_t)i;
   return m;
 }
+
+/* ==================================================== coherence measure
+ * M^64_CPS of Section 4.3: for every group of n consecutive rays (n = 64;
+ * the last group may be shorter), a capsule fitted to the group -- its axis
+ * through the centroid of the origins and the centroid of the termination
+ * points, its two hemispheres and the cone between them with radii equal to
+ * the mean distance of the origins, respectively of the termination points,
+ * from that axis -- and the capsule's surface area
+ *   2 pi r_o^2 + 2 pi r_t^2 + pi (r_o + r_t) sqrt(h^2 + (r_o - r_t)^2),
+ * h the distance between the centroids.  The measure of a ray set is the
+ * mean over its groups.  Readings: a hit terminates at o + t d; a miss at
+ * o + min(tmax, E) d, E the largest extent of the box (where it leaves the
+ * scene); with coincident centroids the axis degenerates to a point and the
+ * distances are taken to that point.  Double precision throughout. */
+static double cps_group(const float* rays, const unsigned char* hits, int64_t first, int64_t cnt, float E) {
+  double co[3] = {0, 0, 0}, ct[3] = {0, 0, 0};
+  double P[64][3], T[64][3];
+  for (int64_t j = 0; j < cnt; ++j) {
+    const float* r = rays + 8 * (first + j);
+    float t;
+    int32_t prim;
+    memcpy(&t, hits + 16 * (first + j), 4);
+    memcpy(&prim, hits + 16 * (first + j) + 4, 4);
+    double len = prim >= 0 ? (double)t : (double)(r[7] < E ? r[7] : E);
+    for (int k = 0; k < 3; ++k) {
+      P[j][k] = (double)r[k];
+      T[j][k] = (double)r[k] + len * (double)r[4 + k];
+      co[k] += P[j][k];
+      ct[k] += T[j][k];
+    }
+  }
+  double axis[3], h2 = 0;
+  for (int k = 0; k < 3; ++k) {
+    co[k] /= (double)cnt;
+    ct[k] /= (double)cnt;
+    axis[k] = ct[k] - co[k];
+    h2 += axis[k] * axis[k];
+  }
+  double h = sqrt(h2);
+  double ro = 0, rt = 0;
+  for (int64_t j = 0; j < cnt; ++j) {
+    double dp[3], dt[3], sp = 0, st = 0;
+    for (int k = 0; k < 3; ++k) {
+      dp[k] = P[j][k] - co[k];
+      dt[k] = T[j][k] - co[k];
+    }
+    if (h > 0) {
+      double ap = 0, at = 0;
+      for (int k = 0; k < 3; ++k) {
+        ap += dp[k] * axis[k] / h;
+        at += dt[k] * axis[k] / h;
+      }
+      for (int k = 0; k < 3; ++k) {
+        double x = dp[k] - ap * axis[k] / h, y = dt[k] - at * axis[k] / h;
+        sp += x * x;
+        st += y * y;
+      }
+    } else {
+      for (int k = 0; k < 3; ++k) {
+        sp += dp[k] * dp[k];
+        st += dt[k] * dt[k];
+      }
+    }
+    ro += sqrt(sp);
+    rt += sqrt(st);
+  }
+  ro /= (double)cnt;
+  rt /= (double)cnt;
+  const double pi = 3.14159265358979323846;
+  return 2 * pi * ro * ro + 2 * pi * rt * rt + pi * (ro + rt) * sqrt(h2 + (ro - rt) * (ro - rt));
+}
+
+/* Per-group measures (ceil(n / 64) of them) and their mean. */
+void orc_cps(const float* rays, const void* hits, int64_t n, const float* box_lo, const float* box_hi,
+             double* per_group, double* mean) {
+  float E = box_extent(box_lo, box_hi);
+  int64_t G = (n + 63) / 64;
+  double s = 0;
+  for (int64_t g = 0; g < G; ++g) {
+    int64_t cnt = n - 64 * g < 64 ? n - 64 * g : 64;
+    per_group[g] = cps_group(rays, (const unsigned char*)hits, 64 * g, cnt, E);
+    s += per_group[g];
+  }
+  *mean = G ? s / (double)G : 0.0;
+}
