@@ -36,6 +36,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "MRays/s incl. reorder vs unsorted trace; sort GB/s; p50/p99 batch latency"
 KEYS = {"none": (0, 32), "od32": (1, 32), "od64": (1, 64), "ot32": (2, 32), "ot64": (2, 64)}
+# the figure's other layouts (32-bit) and the Two Point termination estimates
+METHODS = {"origin": (3, 32), "costa": (4, 32), "aila": (5, 32), "aila_compact": (6, 32), "octahedron": (7, 32),
+           "tp_adaptive32": (8, 32), "tp_adaptive64": (8, 64), "tp_real32": (9, 32)}
 # HBM traffic of the sorted trace launch, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes scaled by a plain copy's readings; valid only while the sources that
 # decide the trace's memory traffic are unchanged (checked by digest).
@@ -43,7 +46,7 @@ TRAFFIC_PROFILE = os.path.join("profiles", "k_trace4_bounce2_1080p_traffic.txt")
 TRAFFIC_SOURCES = ("paper_2506_11273_amd/csrc/trace.hip", "paper_2506_11273_amd/csrc/scene.cpp",
                    "paper_2506_11273_amd/csrc/common.hpp", "paper_2506_11273_amd/csrc/keys_dev.hpp",
                    "paper_2506_11273_amd/csrc/keys.hip", "workloads/gen.c")
-SECTIONS = ("variants", "bounce3", "batch", "serve", "cpu")
+SECTIONS = ("variants", "orders", "bounce3", "batch", "serve", "cpu")
 
 
 def parse():
@@ -215,7 +218,9 @@ def main():
         "roofline": trace_roofline(trace_bytes, trace_ms, n, profiled_traffic(args.key, args.builder)),
     }
     if "variants" not in args.skip:
-        result["variants"] = variants(torch, rr, scene, rays, n, lo, hi, dev, stream, args.steps, unsorted_ms)
+        result["variants"] = variants(torch, rr, scene, rays, n, lo, hi, dev, stream, args.steps, unsorted_ms, uhits)
+    if "orders" not in args.skip:
+        result["coherence"] = orders(torch, rr, scene, rays, n, lo, hi, dev, stream, args.steps, uhits)
     if "bounce3" not in args.skip:
         result["bounce3_2160p"] = bounce3(torch, rr, W, scene, dev, stream, max(5, args.steps // 2))
     if "batch" not in args.skip:
@@ -268,15 +273,20 @@ def trace_roofline(trace_bytes, trace_ms, n, traffic):
             "launch_ms": round(trace_ms, 4)}
 
 
-def variants(torch, rr, scene, rays, n, lo, hi, dev, stream, steps, unsorted_ms):
+def variants(torch, rr, scene, rays, n, lo, hi, dev, stream, steps, unsorted_ms, uhits):
     """The fused entry point for each key kind: hits in key order, hits
-    scattered back to ray order, and tracing through the sorted index."""
+    scattered back to ray order, and tracing through the sorted index; then
+    the figure's other layouts and the adaptive and real Two Point
+    estimates, hits in key order.  The adaptive table is warmed by two calls
+    on the wavefront first and keeps learning in the timed calls (each call
+    adds its traced lengths); the real estimate reads the unsorted trace's
+    hits."""
     out = {}
+    hits = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
     for name, (kind, bits) in KEYS.items():
         p = rr.key_params(kind, bits, lo, hi, 0.25)
         ws = rr.workspace(rr.reorder_workspace_size(n, p), dev)
-        hits = torch.empty((n, 4), dtype=torch.float32, device=dev)
-        cnt = torch.empty(1, dtype=torch.int32, device=dev)
         for flags, tag in ((0, ""), (rr.RR_HITS_ORIGINAL_ORDER, "_scatter_back"), (rr.RR_INDIRECT, "_indirect")):
             def run():
                 rr.rr_reorder_and_trace(scene, rays, p, flags=flags, hits=hits, count=cnt, ws=ws, want_perm=False)
@@ -285,7 +295,68 @@ def variants(torch, rr, scene, rays, n, lo, hi, dev, stream, steps, unsorted_ms)
             out[name + tag] = {"ms": round(ms, 4), "mrays": round(n / (ms * 1e-3) / 1e6, 2),
                                "vs_unsorted": round(unsorted_ms / ms, 3)}
         del ws
+    for name, (kind, bits) in METHODS.items():
+        aux = None
+        if kind == rr.RR_KEY_TWO_POINT_ADAPTIVE:
+            aux = rr.LengthTable(rr.key_params(kind, bits, lo, hi, 0.25))
+        elif kind == rr.RR_KEY_TWO_POINT_REAL:
+            aux = uhits
+        p = rr.key_params(kind, bits, lo, hi, 0.25, aux=aux)
+        ws = rr.workspace(rr.reorder_workspace_size(n, p), dev)
+        def run():
+            rr.rr_reorder_and_trace(scene, rays, p, flags=0, hits=hits, count=cnt, ws=ws, want_perm=False)
+        run(); run()
+        ms = median_ms(torch, stream, run, steps)
+        # the trace alone on this method's order
+        k, idx, _ = rr.rr_compute_keys(rays, p)
+        rr.rr_sort(k, idx, key_bits=bits)
+        srays = rr.rr_gather(rays, idx)
+        tms = median_ms(torch, stream, lambda: rr.rr_trace(scene, srays, hits=hits), steps)
+        out[name] = {"ms": round(ms, 4), "mrays": round(n / (ms * 1e-3) / 1e6, 2),
+                     "vs_unsorted": round(unsorted_ms / ms, 3), "trace_ms": round(tms, 4),
+                     "trace_speedup": round(unsorted_ms / tms, 3)}
+        del ws
     return out
+
+
+def orders(torch, rr, scene, rays, n, lo, hi, dev, stream, steps, uhits):
+    """Trace time and coherence measure M^64_CPS (Section 4.3) of the
+    wavefront in each order: pixel (as generated), shuffled (a seeded random
+    permutation, an incoherent order), and sorted by every key method; both
+    relative to pixel order, with their Pearson correlation over the orders
+    (the paper correlates the two in its coherence study)."""
+    import numpy as np
+    base = rr.key_params(0, 32, lo, hi)
+    out = {}
+    hits = torch.empty((n, 4), dtype=torch.float32, device=dev)
+
+    def measure(r):
+        ms = median_ms(torch, stream, lambda: rr.rr_trace(scene, r, hits=hits), steps)
+        rr.rr_trace(scene, r, hits=hits)
+        _, m = rr.coherence_m64(r, hits, base)
+        return ms, float(m.cpu()[0])
+
+    perm = torch.from_numpy(np.random.default_rng(7).permutation(n)).to(dev)
+    table = rr.LengthTable(rr.key_params(8, 32, lo, hi))
+    # the adaptive table learns from one trace of the wavefront (as after a previous pass)
+    table.accumulate(rays, uhits)
+    rows = {"pixel": rays, "shuffled": rays.index_select(0, perm).contiguous()}
+    for name, (kind, bits) in list(KEYS.items())[1:] + list(METHODS.items()):
+        aux = table if kind == 8 else (uhits if kind == 9 else None)
+        p = rr.key_params(kind, bits, lo, hi, 0.25, aux=aux)
+        k, idx, _ = rr.rr_compute_keys(rays, p)
+        rr.rr_sort(k, idx, key_bits=bits)
+        rows[name] = rr.rr_gather(rays, idx)
+    for name, r in rows.items():
+        ms, m = measure(r)
+        out[name] = {"trace_ms": round(ms, 4), "m64": round(m, 3)}
+    p0 = out["pixel"]
+    for v in out.values():
+        v["rel_trace"] = round(v["trace_ms"] / p0["trace_ms"], 4)
+        v["rel_m64"] = round(v["m64"] / p0["m64"], 4)
+    a = np.array([v["rel_trace"] for v in out.values()])
+    b = np.array([v["rel_m64"] for v in out.values()])
+    return {"orders": out, "pearson_rel_trace_vs_rel_m64": round(float(np.corrcoef(a, b)[0, 1]), 3)}
 
 
 def bounce3(torch, rr, W, scene, dev, stream, steps):

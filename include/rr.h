@@ -196,6 +196,25 @@ rr_status rr_length_table_accumulate(rr_length_cell* table, const rr_ray* rays, 
                                      const rr_hit* hits, int64_t n, const uint32_t* count_dev,
                                      const rr_key_params* p, void* stream);
 
+/* ------------------------------------------------------------- coherence
+ * Ray coherence measure M^64_CPS of Section 4.3 for n rays in the given
+ * order.  Each group of 64 consecutive rays (the last may be shorter) gets
+ * the surface area of a fitted capsule: its axis joins the centroid of the
+ * origins and the centroid of the termination points, and the radii of its
+ * two hemispheres and of the cone between them are the mean distances of the
+ * origins, respectively the termination points, from that axis:
+ *   2 pi r_o^2 + 2 pi r_t^2 + pi (r_o + r_t) sqrt(h^2 + (r_o - r_t)^2),
+ * h the distance between the centroids (with coincident centroids the
+ * distances are taken to that point).  hits[i] is the traced hit of rays[i];
+ * a hit terminates at o + t d, a miss at o + min(tmax, E) d, E the largest
+ * extent of p's box (p's other fields are not used).
+ *  group_out device double[ceil(n / 64)]: the per-group areas.
+ *  mean_out  device double: their mean (0 for n = 0).
+ * Double precision; the sums differ from a sequential evaluation only by
+ * rounding. */
+rr_status rr_coherence_m64(const rr_ray* rays, const rr_hit* hits, int64_t n, const rr_key_params* p,
+                           double* group_out, double* mean_out, void* stream);
+
 /* ------------------------------------------------------------------- sort
  * Section 3.2: stable ascending LSD radix sort of (key, index) pairs, in
  * place.  The result is unique: the lexicographic order of (key, index)

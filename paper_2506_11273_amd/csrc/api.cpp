@@ -207,6 +207,21 @@ rr_status rr_length_table_accumulate(rr_length_cell* table, const rr_ray* rays, 
   return launch_length_accumulate(table, rays, idx, hits, n, count_dev, plan, S(stream));
 }
 
+// -------------------------------------------------------------- coherence
+
+rr_status rr_coherence_m64(const rr_ray* rays, const rr_hit* hits, int64_t n, const rr_key_params* p,
+                           double* group_out, double* mean_out, void* stream) {
+  if (!p || !valid_n(n) || !mean_out || !is_device_ptr(mean_out) || !aligned(mean_out, 8))
+    return RR_ERR_INVALID_ARGUMENT;
+  if (n > 0 && (!is_device_ptr(rays) || !aligned(rays, 16) || !is_device_ptr(hits) || !aligned(hits, 16) ||
+                !group_out || !is_device_ptr(group_out) || !aligned(group_out, 8)))
+    return RR_ERR_INVALID_ARGUMENT;
+  float E = p->box_hi[0] - p->box_lo[0];
+  for (int k = 1; k < 3; ++k)
+    if (p->box_hi[k] - p->box_lo[k] > E) E = p->box_hi[k] - p->box_lo[k];
+  return launch_coherence(rays, hits, n, E, group_out, mean_out, S(stream));
+}
+
 // ------------------------------------------------------------------- sort
 
 rr_status rr_sort_workspace_size(int64_t n_max, uint32_t key_bits, size_t* bytes) {

@@ -74,6 +74,10 @@ rr_status launch_length_accumulate(rr_length_cell* table, const rr_ray* rays, co
                                    const rr_hit* hits, int64_t n_max, const uint32_t* count_dev,
                                    const KeyPlan& plan, hipStream_t st);
 
+// Capsule coherence measure of groups of 64 consecutive rays and its mean.
+rr_status launch_coherence(const rr_ray* rays, const rr_hit* hits, int64_t n, float E, double* group_out,
+                           double* mean_out, hipStream_t st);
+
 // --------------------------------------------------------------- sort
 size_t sort_workspace_bytes(int64_t n_max, uint32_t key_bits, uint32_t digit_bits, uint32_t kpt);
 size_t sort_workspace_bytes_any(int64_t n_max, uint32_t key_bits);

@@ -52,6 +52,7 @@ EXPORTS = (
     "rr_status_string", "rr_device_count",
     "rr_scene_create", "rr_scene_create_ex", "rr_scene_bounds", "rr_scene_info", "rr_scene_destroy",
     "rr_keys_workspace_size", "rr_compute_keys", "rr_length_table_init", "rr_length_table_accumulate",
+    "rr_coherence_m64",
     "rr_sort_workspace_size", "rr_sort", "rr_sort_ex",
     "rr_gather", "rr_scatter_hits", "rr_trace", "rr_trace_ex", "rr_trace_profile",
     "rr_reorder_workspace_size", "rr_reorder_and_trace",
@@ -97,6 +98,7 @@ def load():
         "rr_keys_workspace_size": ([i64, P(sz)], st),
         "rr_compute_keys": ([vp, i64, vp, P(KeyParams), vp, vp, vp, vp, sz, vp], st),
         "rr_length_table_init": ([vp, P(KeyParams), vp], st),
+        "rr_coherence_m64": ([vp, vp, i64, P(KeyParams), vp, vp, vp], st),
         "rr_length_table_accumulate": ([vp, vp, vp, vp, i64, vp, P(KeyParams), vp], st),
         "rr_sort_workspace_size": ([i64, u32, P(sz)], st),
         "rr_sort": ([vp, vp, i64, vp, u32, vp, sz, vp], st),
@@ -406,6 +408,19 @@ def rr_reorder_and_trace(scene: Scene, rays, params: KeyParams, alive=None, flag
                                   _ptr(count, "count", torch.int32, False), flags, _ptr(ws, "workspace"),
                                   ws.numel() * ws.element_size(), _stream(stream)), "rr_reorder_and_trace")
     return hits, perm, count
+
+
+def coherence_m64(rays, hits, params: KeyParams, stream=None):
+    """M^64_CPS of rays in their order (Section 4.3): (per-group areas,
+    mean), float64 device tensors."""
+    torch = _torch()
+    n = _n_rows(rays)
+    groups = torch.empty(max(1, (n + 63) // 64), dtype=torch.float64, device=rays.device)
+    mean = torch.empty(1, dtype=torch.float64, device=rays.device)
+    _check(load().rr_coherence_m64(_ptr(rays, "rays", torch.float32), _ptr(hits, "hits", torch.float32), n,
+                                   ctypes.byref(params), groups.data_ptr(), mean.data_ptr(), _stream(stream)),
+           "rr_coherence_m64")
+    return groups[:(n + 63) // 64], mean
 
 
 def hits_to_numpy(hits) -> np.ndarray:

@@ -217,3 +217,28 @@ def test_batch_mixes_key_methods(rr):
             assert np.array_equal(perm.cpu().numpy().view(np.uint32), want), kind
             alone = rr.hits_to_numpy(rr.rr_trace(sc, rays))
             assert rr.hits_to_numpy(hits).tobytes() == alone.tobytes(), kind
+
+
+# ------------------------------------------------------- coherence measure
+
+def test_coherence_m64_matches_oracle(rr):
+    w = W.city_small(seed=12, width=160, height=90, depth=2)
+    lo, hi = O.scene_box(w.tris)
+    live = O.compact(w.alive)
+    with rr.Scene(w.tris) as sc:
+        p = rr.key_params(rr.RR_KEY_NONE, 32, lo, hi)
+        for n in (1, 63, 64, 65, 1000, len(live)):
+            rn = np.ascontiguousarray(w.rays[live[:n]])
+            rays = to_dev(rn)
+            hits = rr.rr_trace(sc, rays)
+            g, m = rr.coherence_m64(rays, hits, p)
+            gr, mr = O.coherence_m64(rn, rr.hits_to_numpy(hits), lo, hi)
+            gg = g.cpu().numpy()
+            assert len(gg) == len(gr)
+            np.testing.assert_allclose(gg, gr, rtol=1e-9, atol=1e-12)
+            assert abs(float(m.cpu()[0]) - mr) <= 1e-9 * abs(mr) + 1e-12
+        # the measure is deterministic run to run
+        g2, m2 = rr.coherence_m64(rays, hits, p)
+        assert torch.equal(g, g2) and torch.equal(m, m2)
+        e, me = rr.coherence_m64(rays[:0], hits[:0], p)
+        assert float(me.cpu()[0]) == 0.0
