@@ -82,33 +82,41 @@ __device__ __forceinline__ bool slab(float lx, float hx, float ly, float hy, flo
   return n <= f;
 }
 
-// Ray distances to the lower and upper planes of the four children of a
+// Ray distances to the near and far planes of the four children of a
 // quantised node along one axis, in ray-relative form: with delta = p - o,
 // a plane q lies at t = q * (s * inv) + delta * inv, one fused multiply-add
-// per plane.  The rounding of delta, of s * inv and of the products is
-// bounded by (|delta| + 256 s) * |inv| * 2^-22, so every plane is first
-// moved outward by eps = (|delta| + 256 s) * 2^-20: the computed slab then
-// contains the slab of the decoded box, which contains the child's box.
-// (Coordinates are below 1e18 and steps below 2^61, so nothing overflows.)
-__device__ __forceinline__ void qaxis(float p, float s, float o, float inv, uint32_t wlo, uint32_t whi,
-                                      float (&tlo)[4], float (&thi)[4]) {
+// per plane.  Which of the node's two code words holds the near planes
+// depends only on the sign of inv, so the caller passes the words in
+// near/far order.  Every plane is moved outward by
+// eps = |delta| 2^-20 + s 2^-12 (the near planes toward the ray, the far
+// planes away from it: near base (delta*inv - eps*|inv|), far base
+// (delta*inv + eps*|inv|)).  The rounding of delta, of delta*inv, of
+// eps*|inv|, of the bases, of s*inv and of the final fused multiply-add is
+// below (|delta| + 128 s) |inv| 2^-22, a quarter of the move, so the
+// computed slab contains the slab of the decoded box, which contains the
+// child's box.  (Coordinates are below 1e18 and steps below 2^61, so
+// nothing overflows.)
+__device__ __forceinline__ void qaxis(float p, float s, float o, float inv, uint32_t wnear, uint32_t wfar,
+                                      float (&tn)[4], float (&tf)[4]) {
   const float delta = p - o;
-  const float eps = (fabsf(delta) + 256.0f * s) * 0x1p-20f;
+  const float eps = __builtin_fmaf(fabsf(delta), 0x1p-20f, s * 0x1p-12f);
+  const float di = delta * inv;
+  const float ei = eps * fabsf(inv);
+  const float nb = di - ei;
+  const float fb = di + ei;
   const float step = s * inv;
-  const float blo = (delta - eps) * inv;
-  const float bhi = (delta + eps) * inv;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    tlo[j] = __builtin_fmaf((float)((wlo >> (8 * j)) & 0xFFu), step, blo);
-    thi[j] = __builtin_fmaf((float)((whi >> (8 * j)) & 0xFFu), step, bhi);
+    tn[j] = __builtin_fmaf((float)((wnear >> (8 * j)) & 0xFFu), step, nb);
+    tf[j] = __builtin_fmaf((float)((wfar >> (8 * j)) & 0xFFu), step, fb);
   }
 }
 
-// Slab test from precomputed plane distances (see qaxis).
-__device__ __forceinline__ bool qslab(float ax, float bx, float ay, float by, float az, float bz, float tmin,
+// Slab test from near and far plane distances (see qaxis).
+__device__ __forceinline__ bool qslab(float nx, float fx, float ny, float fy, float nz, float fz, float tmin,
                                       float tbest, float* tn) {
-  const float n = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), tmin));
-  float f = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tbest));
+  const float n = fmaxf(fmaxf(nx, ny), fmaxf(nz, tmin));
+  float f = fminf(fminf(fx, fy), fminf(fz, tbest));
   f = __builtin_fmaf(fabsf(f), kFarSlack, f);
   *tn = n;
   return n <= f;
@@ -197,9 +205,13 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
         if ((int)lane == __builtin_ctzll(__ballot(1))) ++st_wave;
       }
     };
+    // While no lane of the wave has spilled (the common case, decided
+    // wave-uniformly) a pop is a plain LDS read, not a load through a
+    // generic pointer.
     auto pop_or_none = [&]() -> int32_t {
       if (sp == 0) return kEmptyChild;
       --sp;
+      if (!__ballot(sp >= kLdsStack)) return lstack[sp * BLOCK];
       return sp < kLdsStack ? lstack[sp * BLOCK] : spill[sp - kLdsStack];
     };
     if (slot < 0) continue;
@@ -222,12 +234,15 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
         const float4 a = N[0], b = N[1], c = N[2];
         cc = *reinterpret_cast<const int4*>(N + 3);
         const uint32_t eb = __float_as_uint(a.w);
-        qaxis(a.x, __uint_as_float((eb & 0xFFu) << 23), R.ox, R.ix, __float_as_uint(b.x), __float_as_uint(b.y),
+        const uint32_t xl = __float_as_uint(b.x), xh = __float_as_uint(b.y);
+        const uint32_t yl = __float_as_uint(b.z), yh = __float_as_uint(b.w);
+        const uint32_t zl = __float_as_uint(c.x), zh = __float_as_uint(c.y);
+        qaxis(a.x, __uint_as_float((eb & 0xFFu) << 23), R.ox, R.ix, R.ix < 0.0f ? xh : xl, R.ix < 0.0f ? xl : xh,
               lox, hix);
-        qaxis(a.y, __uint_as_float(((eb >> 8) & 0xFFu) << 23), R.oy, R.iy, __float_as_uint(b.z),
-              __float_as_uint(b.w), loy, hiy);
-        qaxis(a.z, __uint_as_float(((eb >> 16) & 0xFFu) << 23), R.oz, R.iz, __float_as_uint(c.x),
-              __float_as_uint(c.y), loz, hiz);
+        qaxis(a.y, __uint_as_float(((eb >> 8) & 0xFFu) << 23), R.oy, R.iy, R.iy < 0.0f ? yh : yl,
+              R.iy < 0.0f ? yl : yh, loy, hiy);
+        qaxis(a.z, __uint_as_float(((eb >> 16) & 0xFFu) << 23), R.oz, R.iz, R.iz < 0.0f ? zh : zl,
+              R.iz < 0.0f ? zl : zh, loz, hiz);
         h0 = qslab(lox[0], hix[0], loy[0], hiy[0], loz[0], hiz[0], R.tmin, tbest, &t0) && cc.x != kEmptyChild;
         h1 = qslab(lox[1], hix[1], loy[1], hiy[1], loz[1], hiz[1], R.tmin, tbest, &t1) && cc.y != kEmptyChild;
         h2 = qslab(lox[2], hix[2], loy[2], hiy[2], loz[2], hiz[2], R.tmin, tbest, &t2) && cc.z != kEmptyChild;
@@ -252,14 +267,26 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
         cswap(d0, c0, d2, c2);
         cswap(d1, c1, d3, c3);
         cswap(d1, c1, d2, c2);
-        // push the farther hits, farthest first, so the next nearest pops first
+        // push the farther hits, farthest first, so the next nearest pops
+        // first; while no lane can reach the scratch part (decided
+        // wave-uniformly) the pushes are plain LDS writes
         const int32_t cs[3] = {c1, c2, c3};
+        if (!__ballot(sp + 3 > kLdsStack)) {
 #pragma unroll
-        for (int k = 2; k >= 0; --k) {
-          if (k + 1 < m) {
-            if (sp < kLdsStack) lstack[sp * BLOCK] = cs[k];
-            else spill[sp - kLdsStack] = cs[k];
-            ++sp;
+          for (int k = 2; k >= 0; --k) {
+            if (k + 1 < m) {
+              lstack[sp * BLOCK] = cs[k];
+              ++sp;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int k = 2; k >= 0; --k) {
+            if (k + 1 < m) {
+              if (sp < kLdsStack) lstack[sp * BLOCK] = cs[k];
+              else spill[sp - kLdsStack] = cs[k];
+              ++sp;
+            }
           }
         }
         node = c0;
