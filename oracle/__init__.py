@@ -18,6 +18,8 @@ Reordering Techniques for Faster GPU Ray Tracing", I3D 2020) directly:
                      of groups of 64 consecutive rays and its mean.
 * sort_pairs      -- Section 3.2: key/index pairs sorted by key; the
                      stable order is the lexicographic order of (key, index).
+* local_sort_pairs -- Section 3.2: sorting within segments of consecutive
+                     keys (block-wise) instead of globally.
 * gather          -- Section 3.2: "an additional pass" moving the ray data.
 * BVH.trace       -- closest-hit trace (Section 4.1), brute_force its
                      definition.
@@ -216,6 +218,20 @@ def sort_pairs(k, idx=None):
     idx = np.asarray(idx, dtype=np.uint32)
     order = np.lexsort((idx, k))
     return k[order], idx[order]
+
+
+def local_sort_pairs(k, idx=None, block: int = 1024):
+    """Section 3.2's local sorting: each run of `block` consecutive pairs
+    (the last may be shorter) sorted on its own, stably, by key."""
+    k = np.asarray(k)
+    if idx is None:
+        idx = np.arange(k.shape[0], dtype=np.uint32)
+    idx = np.asarray(idx, dtype=np.uint32)
+    ko = np.empty_like(k)
+    io = np.empty_like(idx)
+    for b in range(0, k.shape[0], block):
+        ko[b:b + block], io[b:b + block] = sort_pairs(k[b:b + block], idx[b:b + block])
+    return ko, io
 
 
 def gather(rays, idx) -> np.ndarray:
