@@ -232,6 +232,16 @@ rr_status rr_sort_ex(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* c
                      uint32_t digit_bits, uint32_t keys_per_thread, void* workspace, size_t ws_bytes,
                      void* stream);
 
+/* Local (block-wise) sorting of Section 3.2: every run of `block` consecutive
+ * pairs (block = 1024, 2048 or 4096; the last run may be shorter) is sorted
+ * on its own, in place, stably by unsigned key, so run r holds the pairs of
+ * positions [r * block, (r + 1) * block) in (key, input position) order.
+ * Cheaper than rr_sort, the resulting order is less coherent.  count_dev as
+ * for rr_sort.  Needs no workspace.  RR_ERR_UNSUPPORTED for another block
+ * size. */
+rr_status rr_local_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                        uint32_t block, void* stream);
+
 /* ----------------------------------------------------------------- gather
  * Section 3.2, "an additional pass" that moves the ray data into key order:
  * out[i] = in[idx[i]] for i < n (n = *count_dev when given, else n_max).
@@ -291,6 +301,11 @@ rr_status rr_trace_profile(rr_scene s, const rr_ray* rays, int64_t n, rr_hit* hi
 /* Trace through the sorted index instead of gathering the rays first
  * (Section 4.4.1, indirect ray access). */
 #define RR_INDIRECT 2u
+/* Sort locally (rr_local_sort) in runs of 1024, 2048 or 4096 keys instead of
+ * device-wide; at most one of these. */
+#define RR_LOCAL_SORT_1024 4u
+#define RR_LOCAL_SORT_2048 8u
+#define RR_LOCAL_SORT_4096 16u
 rr_status rr_reorder_workspace_size(int64_t n_max, const rr_key_params* p, size_t* bytes);
 rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const uint8_t* alive,
                                const rr_key_params* p, rr_hit* hits, uint32_t* perm_out, uint32_t* count_out,

@@ -247,6 +247,17 @@ rr_status rr_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* coun
   return rr_sort_ex(keys, idx, n_max, count_dev, key_bits, 8, 16, workspace, ws_bytes, stream);
 }
 
+rr_status rr_local_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                        uint32_t block, void* stream) {
+  if (!valid_n(n_max) || (key_bits != 32 && key_bits != 64)) return RR_ERR_INVALID_ARGUMENT;
+  if (!local_sort_supported(key_bits, block)) return RR_ERR_UNSUPPORTED;
+  if (n_max == 0) return RR_OK;
+  if (!is_device_ptr(keys) || !is_device_ptr(idx) || !aligned(keys, key_bits / 8) || !aligned(idx, 4))
+    return RR_ERR_INVALID_ARGUMENT;
+  if (count_dev && !is_device_ptr(count_dev)) return RR_ERR_INVALID_ARGUMENT;
+  return launch_local_sort(keys, idx, n_max, count_dev, key_bits, block, S(stream));
+}
+
 // ----------------------------------------------------------------- gather
 
 rr_status rr_gather(const rr_ray* in, const uint32_t* idx, int64_t n_max, const uint32_t* count_dev, rr_ray* out,
@@ -330,7 +341,14 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
                                const rr_key_params* p, rr_hit* hits, uint32_t* perm_out, uint32_t* count_out,
                                uint32_t flags, void* workspace, size_t ws_bytes, void* stream) {
   if (!s || !p || !valid_n(n)) return RR_ERR_INVALID_ARGUMENT;
-  if (flags & ~(RR_HITS_ORIGINAL_ORDER | RR_INDIRECT)) return RR_ERR_INVALID_ARGUMENT;
+  constexpr uint32_t kLocal = RR_LOCAL_SORT_1024 | RR_LOCAL_SORT_2048 | RR_LOCAL_SORT_4096;
+  if (flags & ~(RR_HITS_ORIGINAL_ORDER | RR_INDIRECT | kLocal)) return RR_ERR_INVALID_ARGUMENT;
+  const uint32_t local = flags & kLocal;
+  if (local & (local - 1)) return RR_ERR_INVALID_ARGUMENT;  // at most one block size
+  const uint32_t local_block = local == RR_LOCAL_SORT_1024 ? 1024u
+                               : local == RR_LOCAL_SORT_2048 ? 2048u
+                               : local == RR_LOCAL_SORT_4096 ? 4096u
+                                                             : 0u;
   const bool sorted = p->kind != RR_KEY_NONE;
   KeyPlan plan{};
   if (sorted) {
@@ -372,7 +390,11 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
 
   if (sorted) {
     if ((r = launch_keys(rays, n, alive, plan, keys, idx, cnt, w + L.kscratch, st)) != RR_OK) return r;
-    if ((r = launch_sort(keys, idx, n, cnt, kb, 8, 16, w + L.sortws, L.sort_bytes, st)) != RR_OK) return r;
+    if (local_block) {
+      if ((r = launch_local_sort(keys, idx, n, cnt, kb, local_block, st)) != RR_OK) return r;
+    } else if ((r = launch_sort(keys, idx, n, cnt, kb, 8, 16, w + L.sortws, L.sort_bytes, st)) != RR_OK) {
+      return r;
+    }
   } else {
     if ((r = launch_compact_only(n, alive, idx, cnt, w + L.kscratch, st)) != RR_OK) return r;
   }

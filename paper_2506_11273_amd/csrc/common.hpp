@@ -78,6 +78,11 @@ rr_status launch_length_accumulate(rr_length_cell* table, const rr_ray* rays, co
 rr_status launch_coherence(const rr_ray* rays, const rr_hit* hits, int64_t n, float E, double* group_out,
                            double* mean_out, hipStream_t st);
 
+// Block-wise sort of runs of `block` consecutive pairs (Section 3.2).
+bool local_sort_supported(uint32_t key_bits, uint32_t block);
+rr_status launch_local_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                            uint32_t block, hipStream_t st);
+
 // --------------------------------------------------------------- sort
 size_t sort_workspace_bytes(int64_t n_max, uint32_t key_bits, uint32_t digit_bits, uint32_t kpt);
 size_t sort_workspace_bytes_any(int64_t n_max, uint32_t key_bits);

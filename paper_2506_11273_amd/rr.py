@@ -46,6 +46,9 @@ RR_LENGTH_CELLS = 1 << 20
 
 RR_HITS_ORIGINAL_ORDER = 1
 RR_INDIRECT = 2
+RR_LOCAL_SORT_1024 = 4
+RR_LOCAL_SORT_2048 = 8
+RR_LOCAL_SORT_4096 = 16
 
 # every symbol include/rr.h declares
 EXPORTS = (
@@ -53,7 +56,7 @@ EXPORTS = (
     "rr_scene_create", "rr_scene_create_ex", "rr_scene_bounds", "rr_scene_info", "rr_scene_destroy",
     "rr_keys_workspace_size", "rr_compute_keys", "rr_length_table_init", "rr_length_table_accumulate",
     "rr_coherence_m64",
-    "rr_sort_workspace_size", "rr_sort", "rr_sort_ex",
+    "rr_sort_workspace_size", "rr_sort", "rr_sort_ex", "rr_local_sort",
     "rr_gather", "rr_scatter_hits", "rr_trace", "rr_trace_ex", "rr_trace_profile",
     "rr_reorder_workspace_size", "rr_reorder_and_trace",
 )
@@ -103,6 +106,7 @@ def load():
         "rr_sort_workspace_size": ([i64, u32, P(sz)], st),
         "rr_sort": ([vp, vp, i64, vp, u32, vp, sz, vp], st),
         "rr_sort_ex": ([vp, vp, i64, vp, u32, u32, u32, vp, sz, vp], st),
+        "rr_local_sort": ([vp, vp, i64, vp, u32, u32, vp], st),
         "rr_gather": ([vp, vp, i64, vp, vp, vp], st),
         "rr_scatter_hits": ([vp, vp, i64, vp, vp, vp], st),
         "rr_trace": ([vp, vp, i64, vp, vp, vp], st),
@@ -335,6 +339,17 @@ def rr_sort(keys, idx, count=None, key_bits: Optional[int] = None, digit_bits: i
     _check(L.rr_sort_ex(_ptr(keys, "keys", (torch.int32, torch.int64)), _ptr(idx, "idx", torch.int32), n,
                         _ptr(count, "count", torch.int32, False), kb, digit_bits, keys_per_thread,
                         _ptr(ws, "workspace"), ws.numel() * ws.element_size(), _stream(stream)), "rr_sort")
+    return keys, idx
+
+
+def rr_local_sort(keys, idx, block: int = 1024, count=None, key_bits: Optional[int] = None, stream=None):
+    """Stable in-place sort of every run of `block` consecutive (key, idx)
+    pairs (Section 3.2's local sorting)."""
+    torch = _torch()
+    kb = key_bits or (64 if keys.dtype == torch.int64 else 32)
+    _check(load().rr_local_sort(_ptr(keys, "keys", (torch.int32, torch.int64)), _ptr(idx, "idx", torch.int32),
+                                int(keys.shape[0]), _ptr(count, "count", torch.int32, False), kb, int(block),
+                                _stream(stream)), "rr_local_sort")
     return keys, idx
 
 
