@@ -266,6 +266,14 @@ rr_status rr_scatter_hits(const rr_hit* in, const uint32_t* idx, int64_t n_max, 
  * given). */
 rr_status rr_trace(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t* count_dev, rr_hit* hits,
                    void* stream);
+/* Any-hit (occlusion) trace, for shadow rays (Section 4 traces two shadow
+ * rays per bounce): hits[i] is a miss {+inf, -1, 0, 0} when no triangle
+ * meets ray i in (tmin, tmax), else the record {t, prim, u, v} of one such
+ * triangle -- which one depends on the traversal, so callers should rely on
+ * prim >= 0 only as "occluded" (the record is still exact for that
+ * triangle).  Arguments as for rr_trace. */
+rr_status rr_trace_any(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t* count_dev, rr_hit* hits,
+                       void* stream);
 
 /* rr_trace with an explicit lane-refill threshold (1..64): a wavefront
  * loads new rays into its idle lanes once at least `refill` lanes are idle
@@ -306,6 +314,10 @@ rr_status rr_trace_profile(rr_scene s, const rr_ray* rays, int64_t n, rr_hit* hi
 #define RR_LOCAL_SORT_1024 4u
 #define RR_LOCAL_SORT_2048 8u
 #define RR_LOCAL_SORT_4096 16u
+/* Any-hit tracing (rr_trace_any) instead of closest-hit; refused
+ * (RR_ERR_INVALID_ARGUMENT) with RR_KEY_TWO_POINT_ADAPTIVE, whose table
+ * learns from closest hits. */
+#define RR_ANY_HIT 32u
 rr_status rr_reorder_workspace_size(int64_t n_max, const rr_key_params* p, size_t* bytes);
 rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const uint8_t* alive,
                                const rr_key_params* p, rr_hit* hits, uint32_t* perm_out, uint32_t* count_out,

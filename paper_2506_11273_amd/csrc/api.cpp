@@ -302,6 +302,18 @@ rr_status rr_trace(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t
   return launch_trace(s->d, rays, nullptr, n_max, count_dev, hits, S(stream));
 }
 
+rr_status rr_trace_any(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t* count_dev, rr_hit* hits,
+                       void* stream) {
+  if (!s || !valid_n(n_max)) return RR_ERR_INVALID_ARGUMENT;
+  if (n_max == 0) return RR_OK;
+  if (!is_device_ptr(rays) || !is_device_ptr(hits) || !aligned(rays, 16) || !aligned(hits, 16))
+    return RR_ERR_INVALID_ARGUMENT;
+  if (count_dev && !is_device_ptr(count_dev)) return RR_ERR_INVALID_ARGUMENT;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != s->d.device) return RR_ERR_INVALID_ARGUMENT;
+  return launch_trace_any(s->d, rays, nullptr, n_max, count_dev, hits, S(stream));
+}
+
 rr_status rr_trace_ex(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t* count_dev, rr_hit* hits,
                       uint32_t refill, void* stream) {
   if (!s || !valid_n(n_max) || refill < 1 || refill > 64) return RR_ERR_INVALID_ARGUMENT;
@@ -342,7 +354,8 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
                                uint32_t flags, void* workspace, size_t ws_bytes, void* stream) {
   if (!s || !p || !valid_n(n)) return RR_ERR_INVALID_ARGUMENT;
   constexpr uint32_t kLocal = RR_LOCAL_SORT_1024 | RR_LOCAL_SORT_2048 | RR_LOCAL_SORT_4096;
-  if (flags & ~(RR_HITS_ORIGINAL_ORDER | RR_INDIRECT | kLocal)) return RR_ERR_INVALID_ARGUMENT;
+  if (flags & ~(RR_HITS_ORIGINAL_ORDER | RR_INDIRECT | RR_ANY_HIT | kLocal)) return RR_ERR_INVALID_ARGUMENT;
+  const bool any = (flags & RR_ANY_HIT) != 0;
   const uint32_t local = flags & kLocal;
   if (local & (local - 1)) return RR_ERR_INVALID_ARGUMENT;  // at most one block size
   const uint32_t local_block = local == RR_LOCAL_SORT_1024 ? 1024u
@@ -355,6 +368,7 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
     rr_status st = make_key_plan(p, &plan);
     if (st != RR_OK) return st;
     if (plan.aux && (!is_device_ptr(plan.aux) || !aligned(plan.aux, 16))) return RR_ERR_INVALID_ARGUMENT;
+    if (any && plan.kind == RR_KEY_TWO_POINT_ADAPTIVE) return RR_ERR_INVALID_ARGUMENT;
   }
   hipStream_t st = S(stream);
   if (count_out && !is_device_ptr(count_out)) return RR_ERR_INVALID_ARGUMENT;
@@ -382,7 +396,9 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
 
   if (!sorted && !alive) {
     // identity order: trace in place, both hit orders coincide
-    if ((r = launch_trace(s->d, rays, nullptr, n, nullptr, hits, st)) != RR_OK) return r;
+    r = any ? launch_trace_any(s->d, rays, nullptr, n, nullptr, hits, st)
+            : launch_trace(s->d, rays, nullptr, n, nullptr, hits, st);
+    if (r != RR_OK) return r;
     if (perm_out && (r = launch_iota(perm_out, n, st)) != RR_OK) return r;
     if (count_out && (r = launch_set_u32(count_out, (uint32_t)n, st)) != RR_OK) return r;
     return RR_OK;
@@ -399,11 +415,12 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
     if ((r = launch_compact_only(n, alive, idx, cnt, w + L.kscratch, st)) != RR_OK) return r;
   }
   rr_hit* tout = orig ? shits : hits;
+  auto trace = any ? launch_trace_any : launch_trace;
   if (indirect) {
-    if ((r = launch_trace(s->d, rays, idx, n, cnt, tout, st)) != RR_OK) return r;
+    if ((r = trace(s->d, rays, idx, n, cnt, tout, st)) != RR_OK) return r;
   } else {
     if ((r = launch_gather(rays, idx, n, cnt, srays, st)) != RR_OK) return r;
-    if ((r = launch_trace(s->d, srays, nullptr, n, cnt, tout, st)) != RR_OK) return r;
+    if ((r = trace(s->d, srays, nullptr, n, cnt, tout, st)) != RR_OK) return r;
   }
   if (plan.kind == RR_KEY_TWO_POINT_ADAPTIVE) {
     // Section 3.1.6: the traced lengths update the table after each trace

@@ -120,6 +120,9 @@ rr_status launch_trace_stats(const DeviceScene& s, const rr_ray* rays, int64_t n
 void trace_warm();
 rr_status launch_trace_refill(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
                               const uint32_t* count_dev, rr_hit* hits, uint32_t refill, hipStream_t st);
+// Any-hit (occlusion) trace: some triangle hit in (tmin, tmax), or a miss.
+rr_status launch_trace_any(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
+                           const uint32_t* count_dev, rr_hit* hits, hipStream_t st);
 rr_status launch_trace(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
                        const uint32_t* count_dev, rr_hit* hits, hipStream_t st);
 

@@ -1,7 +1,8 @@
 // Closest-hit trace: software stack traversal of a 4-wide BVH with a
 // two-sided Moller-Trumbore triangle test in binary32 (the nearest-hit
 // kernel of Section 4.1; the paper's method is agnostic to the trace kernel,
-// Section 1).
+// Section 1).  The any-hit variant (the shadow rays of Section 4) stops a
+// ray at the first triangle it finds in (tmin, tmax).
 //
 // Result definition: the lexicographic minimum of (t, primitive id) over the
 // triangles whose test passes with tmin < t < tmax.  The triangle test is
@@ -132,7 +133,7 @@ __device__ __forceinline__ void cswap(float& ta, int32_t& ca, float& tb, int32_t
   ca = c;
 }
 
-template <int BLOCK, bool STATS, bool QNODE>
+template <int BLOCK, bool STATS, bool QNODE, bool ANY>
 __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                                   int32_t root, const float4* __restrict__ rays,
                                                   const uint32_t* __restrict__ idx, const uint32_t* count_dev,
@@ -340,9 +341,16 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
           bprim = prim;
           bu = u;
           bv = v;
+          if constexpr (ANY) break;  // any occluder ends the ray
         }
       }
       leaf = 0;
+      if constexpr (ANY) {
+        if (bprim >= 0) {
+          node = kEmptyChild;
+          sp = 0;
+        }
+      }
       if (node < 0) {
         leaf = node;
         node = pop_or_none();
@@ -365,7 +373,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
 
 constexpr int kTraceBlock = 256;
 
-template <bool STATS, bool QNODE>
+template <bool STATS, bool QNODE, bool ANY>
 uint32_t resident_blocks() {
   static uint32_t cached = 0;
   if (cached) return cached;
@@ -373,7 +381,7 @@ uint32_t resident_blocks() {
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
     cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace4<kTraceBlock, STATS, QNODE>, kTraceBlock, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace4<kTraceBlock, STATS, QNODE, ANY>, kTraceBlock, 0) !=
           hipSuccess ||
       per <= 0)
     per = 4;
@@ -381,28 +389,28 @@ uint32_t resident_blocks() {
   return cached;
 }
 
-template <bool STATS, bool QNODE>
+template <bool STATS, bool QNODE, bool ANY>
 rr_status launch4q(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
                    const uint32_t* count_dev, rr_hit* hits, uint32_t refill, TraceStats* stats, hipStream_t st) {
   // enough waves to fill the device, but at least one full wave of rays each
   const uint64_t waves_needed = (uint64_t)(n_max + kWave - 1) / kWave;
   const uint64_t blocks_needed = (waves_needed + kTraceBlock / kWave - 1) / (kTraceBlock / kWave);
-  const uint32_t blocks = (uint32_t)std::min<uint64_t>(blocks_needed, resident_blocks<STATS, QNODE>());
-  hipLaunchKernelGGL((k_trace4<kTraceBlock, STATS, QNODE>), dim3(blocks), dim3(kTraceBlock), 0, st, s.nodes,
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>(blocks_needed, resident_blocks<STATS, QNODE, ANY>());
+  hipLaunchKernelGGL((k_trace4<kTraceBlock, STATS, QNODE, ANY>), dim3(blocks), dim3(kTraceBlock), 0, st, s.nodes,
                      s.tris, s.root, reinterpret_cast<const float4*>(rays), idx, count_dev, (uint32_t)n_max,
                      reinterpret_cast<float4*>(hits), refill, stats);
   RR_LAUNCH_CHECK();
   return RR_OK;
 }
 
-template <bool STATS>
+template <bool STATS, bool ANY = false>
 rr_status launch4(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
                   const uint32_t* count_dev, rr_hit* hits, uint32_t refill, TraceStats* stats, hipStream_t st) {
   if (n_max <= 0) return RR_OK;
   if (refill < 1) refill = 1;
   if (refill > (uint32_t)kWave) refill = kWave;
-  return s.quantised ? launch4q<STATS, true>(s, rays, idx, n_max, count_dev, hits, refill, stats, st)
-                     : launch4q<STATS, false>(s, rays, idx, n_max, count_dev, hits, refill, stats, st);
+  return s.quantised ? launch4q<STATS, true, ANY>(s, rays, idx, n_max, count_dev, hits, refill, stats, st)
+                     : launch4q<STATS, false, ANY>(s, rays, idx, n_max, count_dev, hits, refill, stats, st);
 }
 
 }  // namespace
@@ -417,11 +425,18 @@ rr_status launch_trace_refill(const DeviceScene& s, const rr_ray* rays, const ui
   return launch4<false>(s, rays, idx, n_max, count_dev, hits, refill, nullptr, st);
 }
 
+rr_status launch_trace_any(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
+                           const uint32_t* count_dev, rr_hit* hits, hipStream_t st) {
+  return launch4<false, true>(s, rays, idx, n_max, count_dev, hits, kDefaultRefill, nullptr, st);
+}
+
 void trace_warm() {
-  (void)resident_blocks<false, false>();
-  (void)resident_blocks<false, true>();
-  (void)resident_blocks<true, false>();
-  (void)resident_blocks<true, true>();
+  (void)resident_blocks<false, false, false>();
+  (void)resident_blocks<false, true, false>();
+  (void)resident_blocks<true, false, false>();
+  (void)resident_blocks<true, true, false>();
+  (void)resident_blocks<false, false, true>();
+  (void)resident_blocks<false, true, true>();
 }
 
 rr_status launch_trace_stats(const DeviceScene& s, const rr_ray* rays, int64_t n_max, rr_hit* hits,

@@ -49,6 +49,7 @@ RR_INDIRECT = 2
 RR_LOCAL_SORT_1024 = 4
 RR_LOCAL_SORT_2048 = 8
 RR_LOCAL_SORT_4096 = 16
+RR_ANY_HIT = 32
 
 # every symbol include/rr.h declares
 EXPORTS = (
@@ -57,7 +58,7 @@ EXPORTS = (
     "rr_keys_workspace_size", "rr_compute_keys", "rr_length_table_init", "rr_length_table_accumulate",
     "rr_coherence_m64",
     "rr_sort_workspace_size", "rr_sort", "rr_sort_ex", "rr_local_sort",
-    "rr_gather", "rr_scatter_hits", "rr_trace", "rr_trace_ex", "rr_trace_profile",
+    "rr_gather", "rr_scatter_hits", "rr_trace", "rr_trace_ex", "rr_trace_any", "rr_trace_profile",
     "rr_reorder_workspace_size", "rr_reorder_and_trace",
 )
 
@@ -111,6 +112,7 @@ def load():
         "rr_scatter_hits": ([vp, vp, i64, vp, vp, vp], st),
         "rr_trace": ([vp, vp, i64, vp, vp, vp], st),
         "rr_trace_profile": ([vp, vp, i64, vp, vp, vp], st),
+        "rr_trace_any": ([vp, vp, i64, vp, vp, vp], st),
         "rr_trace_ex": ([vp, vp, i64, vp, vp, u32, vp], st),
         "rr_reorder_workspace_size": ([i64, P(KeyParams), P(sz)], st),
         "rr_reorder_and_trace": ([vp, vp, i64, vp, P(KeyParams), vp, vp, vp, u32, vp, sz, vp], st),
@@ -385,6 +387,18 @@ def rr_trace(scene: Scene, rays, count=None, hits=None, refill: Optional[int] = 
         _check(load().rr_trace_ex(scene.handle, _ptr(rays, "rays", torch.float32), n,
                                   _ptr(count, "count", torch.int32, False), _ptr(hits, "hits", torch.float32),
                                   int(refill), _stream(stream)), "rr_trace_ex")
+    return hits
+
+
+def rr_trace_any(scene: Scene, rays, count=None, hits=None, stream=None):
+    """Any-hit (occlusion) trace: prim >= 0 where some triangle meets the
+    ray in (tmin, tmax)."""
+    torch = _torch()
+    n = _n_rows(rays)
+    hits = torch.empty((n, 4), dtype=torch.float32, device=rays.device) if hits is None else hits
+    _check(load().rr_trace_any(scene.handle, _ptr(rays, "rays", torch.float32), n,
+                               _ptr(count, "count", torch.int32, False), _ptr(hits, "hits", torch.float32),
+                               _stream(stream)), "rr_trace_any")
     return hits
 
 

@@ -43,3 +43,21 @@ def test_thread_count_does_not_change_output():
 def test_segment_sizes_range():
     s = W.segment_sizes(4)
     assert s.shape == (64,) and s.min() >= 4096 and s.max() < (1 << 21)
+
+
+def test_shadow_rays_end_on_the_light():
+    w = W.city_small(seed=5, width=48, height=27, depth=1)
+    c = w.city
+    lc = (c.nx / 2.0, 30.0, c.nz / 2.0)
+    size = 0.05 * c.extent
+    s = W.shadow_rays(5, 400, w.rays, lc, size, spp=2)
+    assert s.shape == (2 * w.rays.shape[0], 8)
+    assert np.array_equal(s[0::2, 0:3], w.rays[:, 0:3]) and np.array_equal(s[1::2, 0:3], w.rays[:, 0:3])
+    assert np.allclose(np.linalg.norm(s[:, 4:7], axis=1), 1.0, atol=1e-6)
+    end = s[:, 0:3].astype(np.float64) + s[:, 7:8].astype(np.float64) * s[:, 4:7].astype(np.float64)
+    assert np.allclose(end[:, 1], 30.0, atol=1e-3)
+    assert np.all(np.abs(end[:, 0] - lc[0]) <= size / 2 + 1e-3) and np.all(np.abs(end[:, 2] - lc[2]) <= size / 2 + 1e-3)
+    assert np.all(s[:, 3] == 0)
+    # the same seed and stream give the same rays; another stream other ones
+    assert np.array_equal(s, W.shadow_rays(5, 400, w.rays, lc, size, spp=2))
+    assert not np.array_equal(s, W.shadow_rays(5, 401, w.rays, lc, size, spp=2))

@@ -59,6 +59,7 @@ def _get():
         L.wl_city_bounce.restype = i64
         L.wl_city_hit_t.argtypes = [i32, i32, vp, vp, i64, vp, i32]; L.wl_city_hit_t.restype = None
         L.wl_sample.argtypes = [u64, u64, i64, i64, vp]; L.wl_sample.restype = None
+        L.wl_shadow_rays.argtypes = [u64, u64, vp, i64, vp, dbl, i32, vp]; L.wl_shadow_rays.restype = None
         _lib = L
     return _lib
 
@@ -187,6 +188,28 @@ def city_bounce(seed: int, width: int, height: int, depth: int, nx: int = 100, n
 def bounce2_1080p(seed: int = 2) -> Workload:
     """1920x1080 bounce-2 diffuse wavefront on the ~1M-triangle grid city."""
     return city_bounce(seed, 1920, 1080, 1)
+
+
+def shadow_rays(seed: int, stream: int, origins: np.ndarray, light_center, light_size: float, spp: int = 2):
+    """spp shadow rays per origin (rows of a ray array) toward points uniform
+    on a horizontal square light; tmax is the distance to the light point."""
+    o = np.ascontiguousarray(origins, dtype=np.float32)
+    out = np.empty((o.shape[0] * spp, 8), np.float32)
+    lc = np.asarray(light_center, np.float64)
+    _get().wl_shadow_rays(seed, stream, _p(o), o.shape[0], _p(lc), float(light_size), spp, _p(out))
+    return out
+
+
+def shadow_1080p(seed: int = 2) -> Workload:
+    """Two shadow rays per primary hit point of the 1920x1080 view of the
+    grid city (4,147,200 rays) toward a square light of side 5% of the
+    largest scene extent, 30 units above the middle of the city (the paper's
+    path tracer traces two shadow rays per bounce toward an area light of
+    that size)."""
+    w = bounce2_1080p(seed)
+    c = w.city
+    light = (c.nx / 2.0, 30.0, c.nz / 2.0)
+    return Workload("city_shadow_1920x1080x2", w.tris, shadow_rays(seed, 400, w.rays, light, 0.05 * c.extent), None, c)
 
 
 def bounce3_2160p(seed: int = 3, scene_seed: int = 2) -> Workload:

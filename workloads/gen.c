@@ -394,3 +394,31 @@ void wl_city_hit_t(int32_t nx, int32_t nz, const double* heights, const float* r
 void wl_sample(uint64_t seed, uint64_t stream, int64_t n, int64_t pool, int64_t* out) {
   for (int64_t i = 0; i < n; ++i) out[i] = (int64_t)(rng64(seed, stream, (uint64_t)i) % (uint64_t)pool);
 }
+
+/* Shadow rays toward a square area light of side `size` centred at lc and
+ * lying in the plane y = lc[1]: `spp` rays per origin (the origins of
+ * rays_in), light points uniform on the square from the counter generator
+ * (stream `stream`, two draws per ray); direction normalised in double,
+ * tmin 0, tmax the distance to the light point. */
+void wl_shadow_rays(uint64_t seed, uint64_t stream, const float* rays_in, int64_t n, const double* lc, double size,
+                    int32_t spp, float* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    const float* o = rays_in + 8 * i;
+    for (int32_t s = 0; s < spp; ++s) {
+      const int64_t k = i * spp + s;
+      const double u1 = rngu(seed, stream, 2 * (uint64_t)k), u2 = rngu(seed, stream, 2 * (uint64_t)k + 1);
+      const double L[3] = {lc[0] + (u1 - 0.5) * size, lc[1], lc[2] + (u2 - 0.5) * size};
+      const double d[3] = {L[0] - o[0], L[1] - o[1], L[2] - o[2]};
+      const double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      float* r = out + 8 * k;
+      r[0] = o[0];
+      r[1] = o[1];
+      r[2] = o[2];
+      r[3] = 0.0f;
+      r[4] = (float)(d[0] / len);
+      r[5] = (float)(d[1] / len);
+      r[6] = (float)(d[2] / len);
+      r[7] = (float)len;
+    }
+  }
+}
