@@ -46,7 +46,7 @@ TRAFFIC_PROFILE = os.path.join("profiles", "k_trace4_bounce2_1080p_traffic.txt")
 TRAFFIC_SOURCES = ("paper_2506_11273_amd/csrc/trace.hip", "paper_2506_11273_amd/csrc/scene.cpp",
                    "paper_2506_11273_amd/csrc/common.hpp", "paper_2506_11273_amd/csrc/keys_dev.hpp",
                    "paper_2506_11273_amd/csrc/keys.hip", "workloads/gen.c")
-SECTIONS = ("variants", "orders", "bounce3", "batch", "serve", "cpu")
+SECTIONS = ("variants", "orders", "shadow", "bounce3", "batch", "serve", "cpu")
 
 
 def parse():
@@ -221,6 +221,8 @@ def main():
         result["variants"] = variants(torch, rr, scene, rays, n, lo, hi, dev, stream, args.steps, unsorted_ms, uhits)
     if "orders" not in args.skip:
         result["coherence"] = orders(torch, rr, scene, rays, n, lo, hi, dev, stream, args.steps, uhits)
+    if "shadow" not in args.skip:
+        result["shadow_1080p"] = shadow(torch, rr, W, scene, dev, stream, args.steps)
     if "bounce3" not in args.skip:
         result["bounce3_2160p"] = bounce3(torch, rr, W, scene, dev, stream, max(5, args.steps // 2))
     if "batch" not in args.skip:
@@ -295,6 +297,22 @@ def variants(torch, rr, scene, rays, n, lo, hi, dev, stream, steps, unsorted_ms,
             out[name + tag] = {"ms": round(ms, 4), "mrays": round(n / (ms * 1e-3) / 1e6, 2),
                                "vs_unsorted": round(unsorted_ms / ms, 3)}
         del ws
+    # local (block-wise) sorting instead of the device-wide sort
+    for name in ("od32", "ot32", "ot64"):
+        kind, bits = KEYS[name]
+        p = rr.key_params(kind, bits, lo, hi, 0.25)
+        ws = rr.workspace(rr.reorder_workspace_size(n, p), dev)
+        for flag, block in ((rr.RR_LOCAL_SORT_1024, 1024), (rr.RR_LOCAL_SORT_2048, 2048),
+                            (rr.RR_LOCAL_SORT_4096, 4096)):
+            def run():
+                rr.rr_reorder_and_trace(scene, rays, p, flags=flag, hits=hits, count=cnt, ws=ws, want_perm=False)
+            run(); run()
+            ms = median_ms(torch, stream, run, steps)
+            k, idx, _ = rr.rr_compute_keys(rays, p)
+            sort_ms = median_ms(torch, stream, lambda: rr.rr_local_sort(k, idx, block=block, key_bits=bits), steps)
+            out[f"{name}_local{block}"] = {"ms": round(ms, 4), "mrays": round(n / (ms * 1e-3) / 1e6, 2),
+                                           "vs_unsorted": round(unsorted_ms / ms, 3), "sort_ms": round(sort_ms, 4)}
+        del ws
     for name, (kind, bits) in METHODS.items():
         aux = None
         if kind == rr.RR_KEY_TWO_POINT_ADAPTIVE:
@@ -357,6 +375,40 @@ def orders(torch, rr, scene, rays, n, lo, hi, dev, stream, steps, uhits):
     a = np.array([v["rel_trace"] for v in out.values()])
     b = np.array([v["rel_m64"] for v in out.values()])
     return {"orders": out, "pearson_rel_trace_vs_rel_m64": round(float(np.corrcoef(a, b)[0, 1]), 3)}
+
+
+def shadow(torch, rr, W, scene, dev, stream, steps):
+    """Two shadow rays per primary hit point of the 1080p view (4,147,200
+    rays) toward a square light of side 5% of the extent, traced any-hit:
+    unsorted, and reordered by each 32-bit key method (trace alone and the
+    fused call)."""
+    ws_ = W.shadow_1080p()
+    n = ws_.rays.shape[0]
+    rays = torch.from_numpy(ws_.rays).to(dev)
+    lo, hi = scene.bounds()
+    hits = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    un = median_ms(torch, stream, lambda: rr.rr_trace_any(scene, rays, hits=hits), steps)
+    occluded = float((hits[:, 1].view(torch.int32) >= 0).float().mean().cpu())
+    out = {"rays": int(n), "occluded_fraction": round(occluded, 4), "unsorted_trace_ms": round(un, 4),
+           "unsorted_mrays": round(n / (un * 1e-3) / 1e6, 2), "methods": {}}
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    for name, (kind, bits) in [("od32", (1, 32)), ("ot32", (2, 32)), ("origin", (3, 32)), ("costa", (4, 32)),
+                               ("aila", (5, 32)), ("aila_compact", (6, 32)), ("octahedron", (7, 32))]:
+        p = rr.key_params(kind, bits, lo, hi, 0.25)
+        k, idx, _ = rr.rr_compute_keys(rays, p)
+        rr.rr_sort(k, idx, key_bits=bits)
+        srays = rr.rr_gather(rays, idx)
+        tms = median_ms(torch, stream, lambda: rr.rr_trace_any(scene, srays, hits=hits), steps)
+        ws = rr.workspace(rr.reorder_workspace_size(n, p), dev)
+        def run():
+            rr.rr_reorder_and_trace(scene, rays, p, flags=rr.RR_ANY_HIT, hits=hits, count=cnt, ws=ws,
+                                    want_perm=False)
+        run()
+        ms = median_ms(torch, stream, run, steps)
+        out["methods"][name] = {"trace_ms": round(tms, 4), "trace_speedup": round(un / tms, 3),
+                                "fused_ms": round(ms, 4), "fused_vs_unsorted": round(un / ms, 3)}
+        del ws, srays
+    return out
 
 
 def bounce3(torch, rr, W, scene, dev, stream, steps):
