@@ -180,7 +180,7 @@ rr_status enqueue(rr_batch b, uint32_t kb, const rr_batch_config& c, hipStream_t
   RR_LAUNCH_CHECK();
   const SegLayout L = seg_layout(b->cap, (uint32_t)b->max_seg, kb, c.digit_bits, c.keys_per_thread);
   rr_status r = launch_seg_sort(d + b->off_keys, idx, L, d + b->off_ws, shdr, ssegs, nullptr, (uint32_t)b->cap, kb,
-                                c.digit_bits, c.keys_per_thread, st);
+                                c.digit_bits, c.keys_per_thread, true, st);
   if (r != RR_OK) return r;
   hipLaunchKernelGGL(k_batch_gather, dim3(grid), dim3(kBatchBlock), 0, st, hdr, segs, idx, srays);
   RR_LAUNCH_CHECK();

@@ -8,9 +8,12 @@
 //    sequence serves any mix;
 //  * k_seg_hist reads every key once and builds the digit histograms of all
 //    passes per segment;
-//  * k_seg_pass blocks are persistent and take tiles in a fixed order
-//    (block b: tiles b, b + G, b + 2G, ...), so no shared tile counter is
-//    contended.  A tile is ranked by digit with wave64 ballots (a match over
+//  * k_seg_pass blocks are persistent.  A sort that has the device to
+//    itself takes tiles in a fixed order (block b: tiles b, b + G, ...), so
+//    no shared tile counter is contended; the batched layer, whose sorts may
+//    share the device with other kernels, takes them in order from an atomic
+//    counter, so that a tile is only ever held by a running block (each
+//    block takes its next ticket while it works on the current tile).  A tile is ranked by digit with wave64 ballots (a match over
 //    the digit's bits gives each lane its peers; the lowest peer bumps the
 //    wave's digit counter in LDS), its digit counts are published, the
 //    previous tiles of the same segment are looked back for the global
@@ -21,9 +24,11 @@
 //    prefix, so a tile reads its own group's tiles and then whole groups,
 //    kGroup tiles per word.
 //  * Waits never depend on other blocks being resident: an entry that stays
-//    unpublished for kFallbackSpins polls is computed by the waiting thread
-//    itself from the input keys (the fallback of decoupled look-back, Smith,
-//    Levien and Owens 2024), so every wait ends.
+//    unpublished for a bounded number of polls is computed by the waiting
+//    thread itself from the input keys (the fallback of decoupled look-back,
+//    Smith, Levien and Owens 2024), so every wait ends.  With tiles from the
+//    counter every awaited tile is held by a running block, so the bound is
+//    set far out and only guards against the unexpected.
 // Ranking keeps input order within a digit, so the sort is stable and the
 // output is the unique (key, index) lexicographic order for ascending input
 // indices.
@@ -39,7 +44,8 @@ namespace {
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / kWave;
 constexpr uint32_t kGroup = 16;          // tiles per look-back group
-constexpr uint32_t kFallbackSpins = 128; // polls of one unpublished entry before computing it
+constexpr uint32_t kFallbackSpins = 128;       // polls of an unpublished entry before computing it
+constexpr uint32_t kFallbackSpinsCounted = 1u << 16;  // tiles from the counter: waiting is always safe
 constexpr uint32_t kHistUnit = 4096;  // keys per histogram work unit (16 per thread)
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
@@ -83,7 +89,8 @@ __device__ __forceinline__ uint32_t seg_of_tile(const SortSeg* segs, uint32_t ns
 
 // One segment of n = min(*count_dev, n_max) keys; clears its histograms.
 __global__ void k_seg_setup_single(const uint32_t* count_dev, uint32_t n_max, uint32_t tile, SortHdr* hdr,
-                                   SortSeg* segs, uint32_t* __restrict__ hist, uint32_t hist_words) {
+                                   SortSeg* segs, uint32_t* __restrict__ hist, uint32_t hist_words,
+                                   uint32_t* __restrict__ counters, uint32_t n_counters) {
   if (threadIdx.x == 0) {
     uint32_t n = n_max;
     if (count_dev) n = min(*count_dev, n_max);
@@ -92,12 +99,17 @@ __global__ void k_seg_setup_single(const uint32_t* count_dev, uint32_t n_max, ui
     *hdr = SortHdr{1u, tiles, n, 0u};
   }
   for (uint32_t i = threadIdx.x; i < hist_words; i += blockDim.x) hist[i] = 0;
+  for (uint32_t i = threadIdx.x; i < n_counters; i += blockDim.x) counters[i] = 0;
 }
 
-// Clears the histograms of a segment table set up by the caller.
-__global__ void k_seg_init(const SortHdr* hdr, uint32_t* __restrict__ hist, uint32_t words_per_seg) {
+// Clears the histograms of a segment table set up by the caller, and the
+// tile counters.
+__global__ void k_seg_init(const SortHdr* hdr, uint32_t* __restrict__ hist, uint32_t words_per_seg,
+                           uint32_t* __restrict__ counters, uint32_t n_counters) {
   const uint32_t n = hdr->nseg * words_per_seg;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) hist[i] = 0;
+  if (blockIdx.x == 0)
+    for (uint32_t i = threadIdx.x; i < n_counters; i += blockDim.x) counters[i] = 0;
 }
 
 // Digit histograms of every pass per segment.  Blocks take contiguous runs
@@ -184,6 +196,7 @@ struct PassSmem {
   uint32_t global_off[R];
   uint32_t base[R];
   uint32_t scan[kSortWaves];
+  uint32_t ticket;  // next tile, when tiles come from a counter
 };
 
 __device__ __forceinline__ uint32_t load_status(const uint32_t* p) {
@@ -207,11 +220,11 @@ __device__ __noinline__ uint32_t count_digit(const K* __restrict__ keys_in, Sort
 }
 
 // Published value of local tile lt for digit d, waiting for it at most
-// kFallbackSpins polls and counting it from the input after that.
+// `fallback` polls and counting it from the input after that.
 template <typename K, uint32_t kTile>
 __device__ uint32_t tile_word(const uint32_t* status, const K* __restrict__ keys_in, SortSeg sg, uint32_t lt,
-                              uint32_t R, uint32_t shift, uint32_t d) {
-  for (uint32_t spins = 0; spins < kFallbackSpins; ++spins) {
+                              uint32_t R, uint32_t shift, uint32_t d, uint32_t fallback) {
+  for (uint32_t spins = 0; spins < fallback; ++spins) {
     const uint32_t w = load_status(&status[(size_t)(sg.tile_off + lt) * R + d]);
     if (w & ~kStatusCountMask) return w;
     __builtin_amdgcn_s_sleep(2);
@@ -230,7 +243,7 @@ __device__ uint32_t tile_word(const uint32_t* status, const K* __restrict__ keys
 template <typename K, uint32_t kTile>
 __device__ uint32_t look_back(const uint32_t* status, const uint32_t* gstatus, const K* __restrict__ keys_in,
                               SortSeg sg, uint32_t gbase, uint32_t lt, uint32_t R, uint32_t shift, uint32_t d,
-                              uint32_t c, uint32_t* gword) {
+                              uint32_t c, uint32_t* gword, uint32_t fallback) {
   const uint32_t g = lt / kGroup, gs = g * kGroup;
   uint32_t acc = 0;
   bool done = false;
@@ -260,7 +273,7 @@ __device__ uint32_t look_back(const uint32_t* status, const uint32_t* gstatus, c
     acc += a;
     j -= used;
     if (blocked) {
-      if (++spins >= kFallbackSpins) {
+      if (++spins >= fallback) {
         acc += count_digit<K, kTile>(keys_in, sg, (uint32_t)j, shift, R - 1, d);
         --j;
         spins = 0;
@@ -296,10 +309,10 @@ __device__ uint32_t look_back(const uint32_t* status, const uint32_t* gstatus, c
     acc += a;
     G -= used;
     if (blocked) {
-      if (++spins >= kFallbackSpins) {
+      if (++spins >= fallback) {
         // the group's last tile has not published: read its tiles instead
         for (int32_t t = G * (int32_t)kGroup + (int32_t)kGroup - 1; t >= G * (int32_t)kGroup && !done; --t) {
-          const uint32_t v = tile_word<K, kTile>(status, keys_in, sg, (uint32_t)t, R, shift, d);
+          const uint32_t v = tile_word<K, kTile>(status, keys_in, sg, (uint32_t)t, R, shift, d, fallback);
           acc += v & kStatusCountMask;
           if ((v & ~kStatusCountMask) == kStatusPrefix) done = true;
         }
@@ -321,7 +334,8 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
                                                            uint32_t shift, uint32_t passes, uint32_t pass,
                                                            const uint32_t* __restrict__ hist,
                                                            uint32_t* __restrict__ status,
-                                                           uint32_t* __restrict__ gstatus) {
+                                                           uint32_t* __restrict__ gstatus,
+                                                           uint32_t* tile_counter) {
   using S = PassSmem<K, DB, KPT>;
   constexpr uint32_t R = S::R;
   constexpr uint32_t kTile = S::kTile;
@@ -347,7 +361,13 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
       v[j] = ok ? idx_in[base + pos] : 0u;
     }
   };
-  uint32_t tile = blockIdx.x;
+  // tiles in a fixed order, or in order from the counter (tile_counter)
+  const bool counted = tile_counter != nullptr;
+  if (counted) {
+    if (tid == 0) sm.ticket = atomicAdd(tile_counter, 1u);
+    __syncthreads();
+  }
+  uint32_t tile = counted ? sm.ticket : blockIdx.x;
   uint32_t s = 0;
   SortSeg sg{};
   if (tile < T) {
@@ -360,6 +380,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
     const uint32_t lt = tile - sg.tile_off;
     const uint32_t tile_n = min(kTile, sg.n - lt * kTile);
     __syncthreads();  // the previous tile's LDS reads are done; wave_hist is clear
+    if (counted && tid == 0) sm.ticket = atomicAdd(tile_counter, 1u);  // read after the reorder barrier
 
     // ---- rank within the wave, in (j, lane) order
 #pragma unroll
@@ -421,7 +442,8 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
       uint32_t prefix = 0;
       uint32_t* gword = last_of_group ? &gstatus[(size_t)(gbase + lt / kGroup) * R + d] : nullptr;
       if (lt > 0) {
-        prefix = look_back<K, kTile>(status, gstatus, keys_in, sg, gbase, lt, R, shift, d, count, gword);
+        prefix = look_back<K, kTile>(status, gstatus, keys_in, sg, gbase, lt, R, shift, d, count, gword,
+                                     counted ? kFallbackSpinsCounted : kFallbackSpins);
         store_status(&status[(size_t)tile * R + d], kStatusPrefix | (prefix + count));
       }
       if (gword) store_status(gword, kStatusPrefix | (prefix + count));
@@ -447,7 +469,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
 
     // ---- prefetch the next tile, then write this one's digit runs
     const uint32_t seg_end = sg.off + sg.n;
-    const uint32_t next = tile + gridDim.x;
+    const uint32_t next = counted ? sm.ticket : tile + gridDim.x;
     const uint32_t s_next = next < T ? seg_of_tile(segs, nseg, next) : s;
     const SortSeg sg_next = next < T ? segs[s_next] : sg;
     if (next < T) {
@@ -493,7 +515,7 @@ struct Resident {
 
 template <typename K, int DB, int KPT>
 rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, SortHdr* hdr_ext, SortSeg* segs_ext,
-                        const uint32_t* count_dev, uint32_t n_max, hipStream_t st) {
+                        const uint32_t* count_dev, uint32_t n_max, bool counted, hipStream_t st) {
   constexpr uint32_t R = 1u << DB;
   K* kalt = reinterpret_cast<K*>(ws + L.keys_alt);
   uint32_t* ialt = reinterpret_cast<uint32_t*>(ws + L.idx_alt);
@@ -503,23 +525,24 @@ rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, So
   uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
   uint32_t* status = reinterpret_cast<uint32_t*>(ws + L.status);
   uint32_t* gstatus = reinterpret_cast<uint32_t*>(ws + L.gstatus);
+  uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
 
   const uint32_t hist_res = Resident<K, DB, KPT>::hist();
   const uint32_t pass_res = Resident<K, DB, KPT>::pass();
   const uint32_t max_tiles = L.max_tiles;
   if (single)
     hipLaunchKernelGGL(k_seg_setup_single, dim3(1), dim3(256), 0, st, count_dev, n_max, L.tile, hdr, segs, hist,
-                       L.passes * R);
+                       L.passes * R, counters, L.passes);
   else
     hipLaunchKernelGGL(k_seg_init, dim3(std::max(1u, std::min(64u, L.max_seg))), dim3(256), 0, st, hdr, hist,
-                       L.passes * R);
+                       L.passes * R, counters, L.passes);
   // about one unit per block: each block flushes its whole histogram with
   // global atomics, so more blocks than units only adds flush traffic
   const uint32_t hist_units = std::max(1u, max_tiles * L.tile / kHistUnit);
   const uint32_t hist_blocks = std::max(1u, std::min(hist_units, std::min(hist_res, 1024u)));
   hipLaunchKernelGGL((k_seg_hist<K, DB, KPT>), dim3(hist_blocks), dim3(kSortThreads), 0, st, keys, hdr, segs,
                      L.passes, hist, status, L.status_stride, gstatus, L.gstatus_stride);
-  // one resident wave of blocks: block b takes tiles b, b + G, ...
+  // one resident wave of blocks
   const uint32_t pass_blocks = std::max(1u, std::min(max_tiles, pass_res));
   K* src_k = keys;
   uint32_t* src_i = idx;
@@ -528,7 +551,7 @@ rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, So
   for (uint32_t p = 0; p < L.passes; ++p) {
     hipLaunchKernelGGL((k_seg_pass<K, DB, KPT>), dim3(pass_blocks), dim3(kSortThreads), 0, st, src_k, src_i, dst_k,
                        dst_i, hdr, segs, p * DB, L.passes, p, hist, status + (size_t)p * L.status_stride,
-                       gstatus + (size_t)p * L.gstatus_stride);
+                       gstatus + (size_t)p * L.gstatus_stride, counted ? counters + p : nullptr);
     std::swap(src_k, dst_k);
     std::swap(src_i, dst_i);
   }
@@ -555,6 +578,7 @@ SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_
   L.hdr = off; off = align_up(off + sizeof(SortHdr), 256);
   L.segs = off; off = align_up(off + sizeof(SortSeg) * max_seg, 256);
   L.hist = off; off = align_up(off + 4 * (size_t)max_seg * L.passes * R, 256);
+  L.counters = off; off = align_up(off + 4 * (size_t)L.passes, 256);  // tile counter per pass
   L.status = off; off = align_up(off + 4 * (size_t)L.passes * L.status_stride, 256);
   // group words: group g of a segment whose first tile is t0 and index s
   // sits at t0 / kGroup + s + g, below max_tiles / kGroup + max_seg
@@ -598,11 +622,12 @@ void sort_warm(uint32_t key_bits, uint32_t db, uint32_t kpt) {
 
 rr_status launch_seg_sort(void* keys, uint32_t* idx, const SegLayout& L, void* ws, SortHdr* hdr, SortSeg* segs,
                           const uint32_t* count_dev, uint32_t n_max, uint32_t key_bits, uint32_t db, uint32_t kpt,
-                          hipStream_t st) {
+                          bool counted, hipStream_t st) {
   char* w = reinterpret_cast<char*>(ws);
 #define RR_SORT_CASE(KT, DBV, KPTV)                                                                        \
   if (sizeof(KT) * 8 == key_bits && db == DBV && kpt == KPTV)                                            \
-    return seg_sort_impl<KT, DBV, KPTV>(reinterpret_cast<KT*>(keys), idx, L, w, hdr, segs, count_dev, n_max, st);
+    return seg_sort_impl<KT, DBV, KPTV>(reinterpret_cast<KT*>(keys), idx, L, w, hdr, segs, count_dev, n_max, counted, \
+                                        st);
   RR_SORT_CASE(uint32_t, 8, 16)
   RR_SORT_CASE(uint32_t, 8, 8)
   RR_SORT_CASE(uint32_t, 4, 16)
@@ -620,7 +645,8 @@ rr_status launch_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* 
   if (!sort_config_supported(key_bits, db, kpt)) return RR_ERR_UNSUPPORTED;
   const SegLayout L = seg_layout(n_max, 1, key_bits, db, kpt);
   if (ws_bytes < L.total) return RR_ERR_WORKSPACE_TOO_SMALL;
-  return launch_seg_sort(keys, idx, L, ws, nullptr, nullptr, count_dev, (uint32_t)n_max, key_bits, db, kpt, st);
+  return launch_seg_sort(keys, idx, L, ws, nullptr, nullptr, count_dev, (uint32_t)n_max, key_bits, db, kpt, false,
+                         st);
 }
 
 }  // namespace rr

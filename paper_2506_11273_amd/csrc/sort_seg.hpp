@@ -17,7 +17,7 @@ struct SortHdr {
 };
 
 struct SegLayout {
-  size_t keys_alt, idx_alt, hdr, segs, hist, status, gstatus, total;
+  size_t keys_alt, idx_alt, hdr, segs, hist, counters, status, gstatus, total;
   uint32_t passes, tile, max_seg, max_tiles, status_stride, gstatus_stride;
 };
 
@@ -26,9 +26,11 @@ SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_
 // Sorts every segment described by the device header and segment table
 // hdr / segs.  With hdr == nullptr one segment of min(*count_dev, n_max)
 // keys (n_max without count_dev) is set up on the device, in the workspace.
+// counted: the scatter passes take tiles from a counter (for sorts that may
+// share the device with other kernels) instead of in a fixed order.
 rr_status launch_seg_sort(void* keys, uint32_t* idx, const SegLayout& L, void* ws, SortHdr* hdr, SortSeg* segs,
                           const uint32_t* count_dev, uint32_t n_max, uint32_t key_bits, uint32_t db, uint32_t kpt,
-                          hipStream_t st);
+                          bool counted, hipStream_t st);
 
 // Runs the one-time occupancy queries of a sort configuration, so that a
 // later stream capture records kernel launches only.
