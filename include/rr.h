@@ -222,7 +222,10 @@ rr_status rr_coherence_m64(const rr_ray* rays, const rr_hit* hits, int64_t n, co
  * (device uint32) is given, only its first *count_dev pairs are sorted
  * (count_dev must not exceed n_max).  workspace (device, >= the size
  * reported by rr_sort_workspace_size, 256-byte aligned) is scratch that the
- * call overwrites. */
+ * call overwrites.  The scatter passes are tuned for a device they have to
+ * themselves: run beside other long kernels (other streams) they stay
+ * correct but can be much slower; the batched layer (rr_batch.h) schedules
+ * its sorts for sharing. */
 rr_status rr_sort_workspace_size(int64_t n_max, uint32_t key_bits, size_t* bytes);
 rr_status rr_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                   void* workspace, size_t ws_bytes, void* stream);
