@@ -8,7 +8,7 @@
 //  * binned SAH: 32 bins per axis on centroids, surface-area cost, falling
 //    back to the median split when a subtree could otherwise exceed the
 //    trace kernel's stack depth.
-// Leaves hold at most 4 triangles.  Nodes are emitted in depth-first order
+// Leaves hold at most 3 triangles.  Nodes are emitted in depth-first order
 // (a first child follows its parent) as a 4-wide tree, triangles in leaf
 // order with their edges e1 = v1 - v0, e2 = v2 - v0 precomputed in binary32.
 #include <algorithm>
@@ -24,7 +24,7 @@
 namespace rr {
 namespace {
 
-constexpr int kLeafMax = 4;
+constexpr int kLeafMax = 3;  // measured best of 2..6 and SAH-terminated leaves of up to 7
 constexpr int kBins = 32;
 
 struct Box {
@@ -175,10 +175,9 @@ struct Builder {
 // until it has four children or only leaves remain.
 // 8-bit quantised child bounds (compressed 64-byte node): per axis an
 // origin p (the node's lower bound) and a power-of-two step s with
-// 255 * s >= extent; a child bound is stored as q with decoded value
-// fl(p + q * s) (q * s is exact).  q is rounded outward and then checked with
-// that same binary32 arithmetic, so the decoded box always contains the
-// child's exact box.
+// 255 * s >= extent; a child bound is stored as q, the plane at the exact
+// real p + q * s.  q is rounded outward and then checked against that exact
+// sum (see below), so the planes always contain the child's box.
 void quantize_node(const Box* kids, int m, const int32_t* code, float4* out) {
   Box P;
   for (int j = 0; j < m; ++j) P.grow(kids[j]);

@@ -21,7 +21,7 @@
 // a bound decodes to the exact p + q * 2^e, codes chosen by the builder so
 // that these planes enclose the child box.  A child
 // >= 0 is an inner node, kEmptyChild an unused slot, and a child < 0 a leaf
-// ~(first << 3 | count) of at most 4 triangles.
+// ~(first << 3 | count) of at most 7 triangles (the builder makes at most 3).
 // A triangle is 3 x float4 = 48 bytes: (v0, e1.x), (e1.yz, e2.xy),
 // (e2.z, prim id bits, -, -), with e1 = v1 - v0 and e2 = v2 - v0.
 //
