@@ -215,7 +215,8 @@ def main():
         "per_ray": {"inner_visits": round(prof["inner_visits"] / n, 2), "leaf_visits": round(prof["leaf_visits"] / n, 2),
                     "tri_tests": round(prof["tri_tests"] / n, 2)},
         "hits_scatter_back_equal_unsorted": same,
-        "roofline": trace_roofline(trace_bytes, trace_ms, n, profiled_traffic(args.key, args.builder)),
+        "roofline": trace_roofline(trace_bytes, trace_ms, n, profiled_traffic(args.key, args.builder),
+                                   profiled_valu(args.key, args.builder)),
     }
     if "variants" not in args.skip:
         result["variants"] = variants(torch, rr, scene, rays, n, lo, hi, dev, stream, args.steps, unsorted_ms, uhits)
@@ -250,29 +251,55 @@ def sources_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(key: str, builder: int):
-    """Bytes per sorted-trace launch from the committed counter summary, or
-    None when it was taken on other sources or another configuration."""
+def _profile_values(key: str, builder: int) -> dict:
+    """key: value lines of the committed counter summary, or {} when it was
+    taken on other sources or another configuration."""
     try:
         with open(os.path.join(ROOT, TRAFFIC_PROFILE)) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(" "))
     except OSError:
-        return None
+        return {}
     kv = {k.strip(): v.strip() for k, v in kv.items()}
     if kv.get("sources_sha256") != sources_digest() or kv.get("key") != key or kv.get("builder") != str(builder):
-        return None
+        return {}
+    return kv
+
+
+def profiled_traffic(key: str, builder: int):
+    """Bytes per sorted-trace launch from the committed counter summary, or
+    None when it was taken on other sources or another configuration."""
     try:
-        return int(kv["traffic_bytes_per_launch_sorted"])
+        return int(_profile_values(key, builder)["traffic_bytes_per_launch_sorted"])
     except (KeyError, ValueError):
         return None
 
 
-def trace_roofline(trace_bytes, trace_ms, n, traffic):
-    return {"kernel": "k_trace4 (sorted rays)", "bound": "hbm",
-            "achieved": round(trace_bytes / (trace_ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(trace_bytes / (trace_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
-            "traffic": traffic, "algorithmic_bytes_per_launch": trace_bytes, "algorithmic_bytes_per_ray": 48,
-            "launch_ms": round(trace_ms, 4)}
+def profiled_valu(key: str, builder: int):
+    """VALU wave instructions per sorted-trace launch (SQ_INSTS_VALU), from
+    the same committed summary, or None."""
+    try:
+        return int(_profile_values(key, builder)["valu_wave_instructions_per_launch_sorted"])
+    except (KeyError, ValueError):
+        return None
+
+
+# VALU issue capacity without packed FP32: 256 CUs x 4 SIMDs, one wave64
+# instruction per SIMD every 4 cycles, 2.4 GHz.
+VALU_WAVE_INSTR_PER_S = 256 * 4 / 4 * 2.4e9
+
+
+def trace_roofline(trace_bytes, trace_ms, n, traffic, valu_instr):
+    r = {"kernel": "k_trace4 (sorted rays)", "bound": "hbm",
+         "achieved": round(trace_bytes / (trace_ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(trace_bytes / (trace_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+         "traffic": traffic, "algorithmic_bytes_per_launch": trace_bytes, "algorithmic_bytes_per_ray": 48,
+         "launch_ms": round(trace_ms, 4)}
+    # what actually bounds it: VALU issue (counted instructions over the
+    # issue capacity in the live launch time)
+    r["valu_wave_instructions"] = valu_instr
+    r["valu_issue_frac"] = (round(valu_instr / (trace_ms * 1e-3) / VALU_WAVE_INSTR_PER_S, 3)
+                            if valu_instr else None)
+    return r
 
 
 def variants(torch, rr, scene, rays, n, lo, hi, dev, stream, steps, unsorted_ms, uhits):
