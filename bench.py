@@ -46,7 +46,7 @@ TRAFFIC_PROFILE = os.path.join("profiles", "k_trace4_bounce2_1080p_traffic.txt")
 TRAFFIC_SOURCES = ("paper_2506_11273_amd/csrc/trace.hip", "paper_2506_11273_amd/csrc/scene.cpp",
                    "paper_2506_11273_amd/csrc/common.hpp", "paper_2506_11273_amd/csrc/keys_dev.hpp",
                    "paper_2506_11273_amd/csrc/keys.hip", "workloads/gen.c")
-SECTIONS = ("variants", "orders", "shadow", "bounce3", "batch", "serve", "cpu")
+SECTIONS = ("variants", "orders", "shadow", "bounce3", "sorts", "batch", "serve", "cpu")
 
 
 def parse():
@@ -226,6 +226,8 @@ def main():
         result["shadow_1080p"] = shadow(torch, rr, W, scene, dev, stream, args.steps)
     if "bounce3" not in args.skip:
         result["bounce3_2160p"] = bounce3(torch, rr, W, scene, dev, stream, max(5, args.steps // 2))
+    if "sorts" not in args.skip:
+        result["sort_sizes"] = sort_sizes(torch, rr, dev, stream)
     if "batch" not in args.skip:
         result["batched_64_wavefronts"] = batched(torch, rr, W, scene, w, dev, stream)
     scene.close()
@@ -463,6 +465,50 @@ def bounce3(torch, rr, W, scene, dev, stream, steps):
             out[name + tag] = {"ms": round(ms, 4), "mrays": round(live / (ms * 1e-3) / 1e6, 2)}
         assert int(cnt.cpu()[0]) == live
         del ws
+    return out
+
+
+def sort_sizes(torch, rr, dev, stream, reps=7):
+    """rr_sort of seeded uniform random keys with indices 0..n-1 at the two
+    wavefront sizes and at 64M pairs (beyond the 256 MB last-level cache),
+    32- and 64-bit keys, against the HBM roofline of the 8-bit schedule; each
+    result is checked (keys non-decreasing as unsigned words, equal keys in
+    ascending index order, indices a permutation)."""
+    out = {}
+    for n in (2073600, 8294400, 67108864):
+        for bits in (32, 64):
+            g = torch.Generator(device=dev)
+            g.manual_seed(n + bits)
+            dt = torch.int64 if bits == 64 else torch.int32
+            lo, hi = (-(1 << 63), (1 << 63) - 1) if bits == 64 else (-(1 << 31), (1 << 31) - 1)
+            k0 = torch.randint(lo, hi, (n,), dtype=dt, device=dev, generator=g)
+            i0 = torch.arange(n, dtype=torch.int32, device=dev)
+            k = torch.empty_like(k0)
+            i = torch.empty_like(i0)
+            ws = rr.workspace(rr.sort_workspace_size(n, bits), dev)
+            times = []
+            for _ in range(reps):
+                k.copy_(k0)
+                i.copy_(i0)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                rr.rr_sort(k, i, key_bits=bits, ws=ws)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            ms = float(np.median(times[1:]))
+            flip = k ^ torch.tensor(lo, dtype=dt, device=dev)  # unsigned order as signed order
+            ok = bool((flip[1:] >= flip[:-1]).all())
+            ties = flip[1:] == flip[:-1]
+            ok = ok and bool((i[1:][ties] > i[:-1][ties]).all())
+            ok = ok and bool(torch.equal(torch.sort(i).values, i0))
+            ok = ok and bool(torch.equal(k0[i.long()], k))
+            b = sort_algorithmic_bytes(n, bits)
+            out[f"u{bits}_n{n}"] = {"ms": round(ms, 4), "gbs": round(b / (ms * 1e-3) / 1e9, 1),
+                                    "roofline_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3), "ok": ok}
+            del k0, i0, k, i, ws, flip, ties
+            torch.cuda.empty_cache()
     return out
 
 

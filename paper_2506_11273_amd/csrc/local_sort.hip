@@ -10,6 +10,7 @@
 // after every real key (stably after real all-ones keys) and are not
 // written.
 #include "common.hpp"
+#include "wave.hpp"
 
 namespace rr {
 namespace {
@@ -17,10 +18,6 @@ namespace {
 constexpr int kLsThreads = 1024;
 constexpr int kLsWaves = kLsThreads / kWave;
 constexpr int kRadix = 256;
-
-__device__ __forceinline__ uint32_t ls_lanes_below(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
 
 template <typename K, int B>
 struct LocalSmem {
@@ -55,27 +52,23 @@ __global__ __launch_bounds__(kLsThreads) void k_local_sort(K* __restrict__ keys,
     const uint32_t shift = pass * 8;
     for (uint32_t i = tid; i < kLsWaves * kRadix; i += kLsThreads) (&sm.wave_hist[0][0])[i] = 0;
     __syncthreads();
-    // ---- rank within the wave, in (slot, lane) order
+    // ---- rank within the wave, in (slot, lane) order: the lowest lane of
+    // each group of equal digits adds the group's size to the wave's count
+    // with an LDS atomic (the leaders of one slot hold distinct digits, and
+    // a wave's LDS operations take effect in order); the group's lanes take
+    // the returned count once every slot has been issued
+    uint32_t old[KPT];
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       const uint32_t d = (uint32_t)(k[j] >> shift) & (kRadix - 1);
-      uint64_t peers = ~0ull;
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = __ballot(bit);
-        peers &= bit ? m : ~m;
-      }
-      const uint32_t below = ls_lanes_below(peers);
-      const int leader = (int)__builtin_ctzll(peers);
-      uint32_t old = 0;
-      if ((int)lane == leader) {
-        old = sm.wave_hist[wave][d];
-        sm.wave_hist[wave][d] = old + (uint32_t)__popcll(peers);
-      }
-      old = __shfl(old, leader, kWave);
-      rank[j] = old + below;
+      const uint64_t peers = match_digit<8>(d, ~0ull);
+      const uint32_t leader = (uint32_t)__builtin_ctzll(peers);
+      rank[j] = lanes_below(peers) | (leader << 16);
+      old[j] = 0;
+      if (lane == leader) old[j] = atomicAdd(&sm.wave_hist[wave][d], (uint32_t)__popcll(peers));
     }
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) rank[j] = (rank[j] & 0xFFFFu) + __shfl(old[j], (int)(rank[j] >> 16), kWave);
     __syncthreads();
     // ---- per digit: offsets of the waves, then the digits' bases
     if (tid < kRadix) {

@@ -37,6 +37,7 @@
 
 #include "common.hpp"
 #include "sort_seg.hpp"
+#include "wave.hpp"
 
 namespace rr {
 namespace {
@@ -47,10 +48,7 @@ constexpr uint32_t kGroup = 16;          // tiles per look-back group
 constexpr uint32_t kFallbackSpins = 128;       // polls of an unpublished entry before computing it
 constexpr uint32_t kFallbackSpinsCounted = 1u << 16;  // tiles from the counter: waiting is always safe
 constexpr uint32_t kHistUnit = 4096;  // keys per histogram work unit (16 per thread)
-
-__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
+constexpr uint32_t kHistCopies = 8;   // histogram copies of a single-segment sort (one per XCD)
 
 // Exclusive scan of one value per thread over a 256-thread block (wave
 // shuffles, then the four wave totals); s needs kSortWaves words.
@@ -87,10 +85,13 @@ __device__ __forceinline__ uint32_t seg_of_tile(const SortSeg* segs, uint32_t ns
   return lo;
 }
 
-// One segment of n = min(*count_dev, n_max) keys; clears its histograms.
+// One segment of n = min(*count_dev, n_max) keys; clears its histograms
+// (all copies, spread over the blocks).
 __global__ void k_seg_setup_single(const uint32_t* count_dev, uint32_t n_max, uint32_t tile, SortHdr* hdr,
                                    SortSeg* segs, uint32_t* __restrict__ hist, uint32_t hist_words,
                                    uint32_t* __restrict__ counters, uint32_t n_counters) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < hist_words; i += gridDim.x * blockDim.x) hist[i] = 0;
+  if (blockIdx.x != 0) return;
   if (threadIdx.x == 0) {
     uint32_t n = n_max;
     if (count_dev) n = min(*count_dev, n_max);
@@ -98,7 +99,6 @@ __global__ void k_seg_setup_single(const uint32_t* count_dev, uint32_t n_max, ui
     segs[0] = SortSeg{0u, n, 0u, tiles};
     *hdr = SortHdr{1u, tiles, n, 0u};
   }
-  for (uint32_t i = threadIdx.x; i < hist_words; i += blockDim.x) hist[i] = 0;
   for (uint32_t i = threadIdx.x; i < n_counters; i += blockDim.x) counters[i] = 0;
 }
 
@@ -115,12 +115,14 @@ __global__ void k_seg_init(const SortHdr* hdr, uint32_t* __restrict__ hist, uint
 // Digit histograms of every pass per segment.  Blocks take contiguous runs
 // of kHistUnit-key units (a unit never straddles a segment), load a unit's
 // keys before counting them, and flush their LDS counts when the segment
-// changes; the look-back words (tile and group) the passes will use are
-// cleared too.
+// changes, block b into histogram copy b % copies (blocks are dealt to the
+// XCDs in turn, so with 8 copies each copy takes the atomics of one XCD and
+// no device word takes more than about blocks / copies of them); the
+// look-back words (tile and group) the passes will use are cleared too.
 template <typename K, int DB, int KPT>
 __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__ keys, const SortHdr* hdr,
                                                            const SortSeg* __restrict__ segs, uint32_t passes,
-                                                           uint32_t* __restrict__ hist,
+                                                           uint32_t copies, uint32_t* __restrict__ hist,
                                                            uint32_t* __restrict__ status,
                                                            uint32_t status_pass_stride,
                                                            uint32_t* __restrict__ gstatus,
@@ -136,6 +138,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
   const uint32_t nseg = hdr->nseg, T = hdr->total_tiles;
   const uint32_t U = T * kUnitsPerTile;
   const uint32_t words = passes * R;
+  const uint32_t copy = blockIdx.x % copies;
   for (uint32_t i = threadIdx.x; i < words; i += kSortThreads) s_h[i] = 0;
   __syncthreads();
   const uint32_t u0 = (uint32_t)(((uint64_t)blockIdx.x * U) / gridDim.x);
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
     if (s != cur) {
       __syncthreads();
       for (uint32_t i = threadIdx.x; i < words; i += kSortThreads) {
-        if (s_h[i]) atomicAdd(&hist[(size_t)cur * words + i], s_h[i]);
+        if (s_h[i]) atomicAdd(&hist[((size_t)cur * copies + copy) * words + i], s_h[i]);
         s_h[i] = 0;
       }
       __syncthreads();
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
   __syncthreads();
   if (u0 < u1)
     for (uint32_t i = threadIdx.x; i < words; i += kSortThreads)
-      if (s_h[i]) atomicAdd(&hist[(size_t)cur * words + i], s_h[i]);
+      if (s_h[i]) atomicAdd(&hist[((size_t)cur * copies + copy) * words + i], s_h[i]);
   // clear the look-back words of the tiles and groups this sort will use
   const uint32_t stride = gridDim.x * kSortThreads;
   const uint32_t groups = T / kGroup + nseg;
@@ -191,9 +194,8 @@ struct PassSmem {
   static constexpr uint32_t kTile = kSortThreads * KPT;
   K keys[kTile];
   uint32_t idx[kTile];
-  uint32_t wave_hist[kSortWaves][R];
-  uint32_t local_off[R];
-  uint32_t global_off[R];
+  uint32_t wave_hist[kSortWaves][R];  // per-wave digit counts, then their tile positions
+  uint32_t delta[R];                  // output position minus tile position, per digit
   uint32_t base[R];
   uint32_t scan[kSortWaves];
   uint32_t ticket;  // next tile, when tiles come from a counter
@@ -332,7 +334,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
                                                            K* __restrict__ keys_out, uint32_t* __restrict__ idx_out,
                                                            const SortHdr* hdr, const SortSeg* __restrict__ segs,
                                                            uint32_t shift, uint32_t passes, uint32_t pass,
-                                                           const uint32_t* __restrict__ hist,
+                                                           uint32_t copies, const uint32_t* __restrict__ hist,
                                                            uint32_t* __restrict__ status,
                                                            uint32_t* __restrict__ gstatus,
                                                            uint32_t* tile_counter) {
@@ -353,12 +355,14 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
   uint32_t v[KPT];
   uint32_t rank[KPT];
   auto load_tile = [&](uint32_t base, uint32_t tile_n) {
+    const K* kb = keys_in + base;  // block-uniform tile start
+    const uint32_t* ib = idx_in + base;
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       const uint32_t pos = wave * (KPT * kWave) + j * kWave + lane;
       const bool ok = pos < tile_n;
-      k[j] = ok ? keys_in[base + pos] : (K)0;
-      v[j] = ok ? idx_in[base + pos] : 0u;
+      k[j] = ok ? kb[pos] : (K)0;
+      v[j] = ok ? ib[pos] : 0u;
     }
   };
   // tiles in a fixed order, or in order from the counter (tile_counter)
@@ -382,57 +386,59 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
     __syncthreads();  // the previous tile's LDS reads are done; wave_hist is clear
     if (counted && tid == 0) sm.ticket = atomicAdd(tile_counter, 1u);  // read after the reorder barrier
 
-    // ---- rank within the wave, in (j, lane) order
+    // ---- rank within the wave, in (j, lane) order.  The lowest lane of
+    // each group of equal digits adds the group's size to the wave's count
+    // with an LDS atomic (the leaders of one step hold distinct digits, and
+    // a wave's LDS operations take effect in order), and the group's lanes
+    // take the count it returned once every step has been issued.
+    uint32_t old[KPT];
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       const uint32_t pos = wave * (KPT * kWave) + j * kWave + lane;
       const bool ok = pos < tile_n;
       const uint32_t d = (uint32_t)(k[j] >> shift) & (R - 1);
-      uint64_t peers = __ballot(ok);
-#pragma unroll
-      for (int b = 0; b < DB; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = __ballot(bit);
-        peers &= bit ? m : ~m;
-      }
-      const uint32_t below = lanes_below(peers);
-      const int leader = ok ? (int)__builtin_ctzll(peers) : (int)lane;
-      uint32_t old = 0;
-      if (ok && (int)lane == leader) {
-        old = sm.wave_hist[wave][d];
-        sm.wave_hist[wave][d] = old + (uint32_t)__popcll(peers);
-      }
-      old = __shfl(old, leader, kWave);
-      rank[j] = old + below;
+      const uint64_t peers = match_digit<DB>(d, __ballot(ok));
+      const uint32_t leader = ok ? (uint32_t)__builtin_ctzll(peers) : lane;
+      rank[j] = lanes_below(peers) | (leader << 16);
+      old[j] = 0;
+      if (ok && lane == leader) old[j] = atomicAdd(&sm.wave_hist[wave][d], (uint32_t)__popcll(peers));
     }
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) rank[j] = (rank[j] & 0xFFFFu) + __shfl(old[j], (int)(rank[j] >> 16), kWave);
     __syncthreads();
 
     // ---- digit bases of this segment and pass: offset + exclusive prefix
     if (s != cur) {  // block-uniform
       uint32_t total;
-      const uint32_t h = tid < R ? hist[((size_t)s * passes + pass) * R + tid] : 0u;
+      uint32_t h = 0;
+      if (tid < R)
+        for (uint32_t c = 0; c < copies; ++c) h += hist[(((size_t)s * copies + c) * passes + pass) * R + tid];
       const uint32_t ex = block_scan_256(h, sm.scan, &total);
       if (tid < R) sm.base[tid] = sg.off + ex;
       cur = s;
     }
 
-    // ---- per digit: wave offsets, tile count, publication
+    // ---- per digit: wave offsets, tile count, publication, then each
+    // wave's first tile position of the digit
     uint32_t count = 0;
+    uint32_t wpre[kSortWaves];
     if (tid < R) {
       const uint32_t d = tid;
       uint32_t c = 0;
 #pragma unroll
       for (int w = 0; w < kSortWaves; ++w) {
-        const uint32_t t = sm.wave_hist[w][d];
-        sm.wave_hist[w][d] = c;
-        c += t;
+        wpre[w] = c;
+        c += sm.wave_hist[w][d];
       }
       count = c;
       store_status(&status[(size_t)tile * R + d], (lt == 0 ? kStatusPrefix : kStatusAggregate) | c);
     }
     uint32_t total;
     const uint32_t local = block_scan_256(count, sm.scan, &total);
-    if (tid < R) sm.local_off[tid] = local;
+    if (tid < R) {
+#pragma unroll
+      for (int w = 0; w < kSortWaves; ++w) sm.wave_hist[w][tid] = local + wpre[w];
+    }
 
     // ---- look-back for the global offsets
     if (tid < R) {
@@ -447,7 +453,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
         store_status(&status[(size_t)tile * R + d], kStatusPrefix | (prefix + count));
       }
       if (gword) store_status(gword, kStatusPrefix | (prefix + count));
-      sm.global_off[d] = sm.base[d] + prefix;
+      sm.delta[d] = sm.base[d] + prefix - local;  // modulo 2^32; the sum below is in range
     }
     __syncthreads();
 
@@ -457,7 +463,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
       const uint32_t pos = wave * (KPT * kWave) + j * kWave + lane;
       if (pos < tile_n) {
         const uint32_t d = (uint32_t)(k[j] >> shift) & (R - 1);
-        const uint32_t at = sm.local_off[d] + sm.wave_hist[wave][d] + rank[j];
+        const uint32_t at = sm.wave_hist[wave][d] + rank[j];
         if (at < kTile) {
           sm.keys[at] = k[j];
           sm.idx[at] = v[j];
@@ -479,7 +485,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
     for (uint32_t p = tid; p < tile_n; p += kSortThreads) {
       const K key = sm.keys[p];
       const uint32_t d = (uint32_t)(key >> shift) & (R - 1);
-      const uint32_t out = sm.global_off[d] + (p - sm.local_off[d]);
+      const uint32_t out = sm.delta[d] + p;
       if (out < seg_end) {  // always true when the histograms are consistent
         keys_out[out] = key;
         idx_out[out] = sm.idx[p];
@@ -530,18 +536,19 @@ rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, So
   const uint32_t hist_res = Resident<K, DB, KPT>::hist();
   const uint32_t pass_res = Resident<K, DB, KPT>::pass();
   const uint32_t max_tiles = L.max_tiles;
+  const uint32_t hist_words = L.hist_copies * L.passes * R;  // per segment
   if (single)
-    hipLaunchKernelGGL(k_seg_setup_single, dim3(1), dim3(256), 0, st, count_dev, n_max, L.tile, hdr, segs, hist,
-                       L.passes * R, counters, L.passes);
+    hipLaunchKernelGGL(k_seg_setup_single, dim3(L.hist_copies), dim3(256), 0, st, count_dev, n_max, L.tile, hdr,
+                       segs, hist, hist_words, counters, L.passes);
   else
     hipLaunchKernelGGL(k_seg_init, dim3(std::max(1u, std::min(64u, L.max_seg))), dim3(256), 0, st, hdr, hist,
-                       L.passes * R, counters, L.passes);
+                       hist_words, counters, L.passes);
   // about one unit per block: each block flushes its whole histogram with
   // global atomics, so more blocks than units only adds flush traffic
   const uint32_t hist_units = std::max(1u, max_tiles * L.tile / kHistUnit);
   const uint32_t hist_blocks = std::max(1u, std::min(hist_units, std::min(hist_res, 1024u)));
   hipLaunchKernelGGL((k_seg_hist<K, DB, KPT>), dim3(hist_blocks), dim3(kSortThreads), 0, st, keys, hdr, segs,
-                     L.passes, hist, status, L.status_stride, gstatus, L.gstatus_stride);
+                     L.passes, L.hist_copies, hist, status, L.status_stride, gstatus, L.gstatus_stride);
   // one resident wave of blocks
   const uint32_t pass_blocks = std::max(1u, std::min(max_tiles, pass_res));
   K* src_k = keys;
@@ -550,7 +557,8 @@ rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, So
   uint32_t* dst_i = ialt;
   for (uint32_t p = 0; p < L.passes; ++p) {
     hipLaunchKernelGGL((k_seg_pass<K, DB, KPT>), dim3(pass_blocks), dim3(kSortThreads), 0, st, src_k, src_i, dst_k,
-                       dst_i, hdr, segs, p * DB, L.passes, p, hist, status + (size_t)p * L.status_stride,
+                       dst_i, hdr, segs, p * DB, L.passes, p, L.hist_copies, hist,
+                       status + (size_t)p * L.status_stride,
                        gstatus + (size_t)p * L.gstatus_stride, counted ? counters + p : nullptr);
     std::swap(src_k, dst_k);
     std::swap(src_i, dst_i);
@@ -577,7 +585,8 @@ SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_
   L.idx_alt = off; off = align_up(off + 4 * (size_t)n_max, 256);
   L.hdr = off; off = align_up(off + sizeof(SortHdr), 256);
   L.segs = off; off = align_up(off + sizeof(SortSeg) * max_seg, 256);
-  L.hist = off; off = align_up(off + 4 * (size_t)max_seg * L.passes * R, 256);
+  L.hist_copies = max_seg == 1 ? kHistCopies : 1u;
+  L.hist = off; off = align_up(off + 4 * (size_t)max_seg * L.hist_copies * L.passes * R, 256);
   L.counters = off; off = align_up(off + 4 * (size_t)L.passes, 256);  // tile counter per pass
   L.status = off; off = align_up(off + 4 * (size_t)L.passes * L.status_stride, 256);
   // group words: group g of a segment whose first tile is t0 and index s

@@ -16,9 +16,12 @@ struct SortHdr {
   uint32_t nseg, total_tiles, total_keys, pad;
 };
 
+// hist holds hist_copies copies of every segment's digit histograms
+// (passes x radix words each); a single-segment sort spreads its histogram
+// flush over several copies, summed again by the scatter passes.
 struct SegLayout {
   size_t keys_alt, idx_alt, hdr, segs, hist, counters, status, gstatus, total;
-  uint32_t passes, tile, max_seg, max_tiles, status_stride, gstatus_stride;
+  uint32_t passes, tile, max_seg, max_tiles, status_stride, gstatus_stride, hist_copies;
 };
 
 SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_t db, uint32_t kpt);
