@@ -44,7 +44,9 @@ namespace {
 
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / kWave;
-constexpr uint32_t kGroup = 16;          // tiles per look-back group
+constexpr uint32_t kGroup = 8;           // tiles per look-back group
+constexpr uint32_t kTileWindow = kGroup - 1;  // tile words read per look-back round
+constexpr uint32_t kGroupWindow = kGroup;     // group words read per look-back round
 constexpr uint32_t kFallbackSpins = 128;       // polls of an unpublished entry before computing it
 constexpr uint32_t kFallbackSpinsCounted = 1u << 16;  // tiles from the counter: waiting is always safe
 constexpr uint32_t kHistUnit = 4096;  // keys per histogram work unit (16 per thread)
@@ -253,15 +255,15 @@ __device__ uint32_t look_back(const uint32_t* status, const uint32_t* gstatus, c
   int32_t j = (int32_t)lt - 1;  // nearest tile not yet accounted for
   while (!done && j >= (int32_t)gs) {
     const int32_t lim = j - (int32_t)gs + 1;  // valid entries in the window
-    uint32_t w[kGroup - 1];
+    uint32_t w[kTileWindow];
 #pragma unroll
-    for (int q = 0; q < (int)kGroup - 1; ++q)
+    for (int q = 0; q < (int)kTileWindow; ++q)
       w[q] = q < lim ? load_status(&status[(size_t)(sg.tile_off + j - q) * R + d]) : 0u;
     uint32_t a = 0;
     int used = 0;
     bool blocked = false;
 #pragma unroll
-    for (int q = 0; q < (int)kGroup - 1; ++q) {
+    for (int q = 0; q < (int)kTileWindow; ++q) {
       if (done || blocked || q >= lim) continue;
       const uint32_t flag = w[q] & ~kStatusCountMask;
       if (flag == 0) {
@@ -289,15 +291,15 @@ __device__ uint32_t look_back(const uint32_t* status, const uint32_t* gstatus, c
   spins = 0;
   while (!done && G >= 0) {
     const int32_t lim = G + 1;
-    uint32_t w[kGroup];
+    uint32_t w[kGroupWindow];
 #pragma unroll
-    for (int q = 0; q < (int)kGroup; ++q)
+    for (int q = 0; q < (int)kGroupWindow; ++q)
       w[q] = q < lim ? load_status(&gstatus[(size_t)(gbase + G - q) * R + d]) : 0u;
     uint32_t a = 0;
     int used = 0;
     bool blocked = false;
 #pragma unroll
-    for (int q = 0; q < (int)kGroup; ++q) {
+    for (int q = 0; q < (int)kGroupWindow; ++q) {
       if (done || blocked || q >= lim) continue;
       const uint32_t flag = w[q] & ~kStatusCountMask;
       if (flag == 0) {

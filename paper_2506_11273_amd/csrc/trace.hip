@@ -44,6 +44,7 @@ constexpr float kFarSlack = 0x1p-16f;
 constexpr float kTinyDir = 1e-20f;
 constexpr int kLdsStack = 16;
 constexpr int kSpillStack = kTraceStack4 - kLdsStack;
+constexpr uint32_t kPacket = 64;  // consecutive ray slots a wave takes in turn
 
 __device__ __forceinline__ uint32_t read_count(const uint32_t* count_dev, uint32_t n_max) {
   if (!count_dev) return n_max;
@@ -149,11 +150,21 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
   // of the BVH its L2 must hold small when the rays are spatially sorted.
   const uint32_t nb = gridDim.x, q = nb / kXcds, rem = nb % kXcds;
   const uint32_t x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
-  const uint32_t lb = (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + j;
-  const uint32_t w = lb * (BLOCK / kWave) + threadIdx.x / kWave;
-  // this wave's contiguous chunk of ray slots
-  uint32_t next = (uint32_t)(((uint64_t)w * n) / waves);
-  const uint32_t end = (uint32_t)(((uint64_t)(w + 1) * n) / waves);
+  const uint32_t xb0 = x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q;  // XCD's first block
+  const uint32_t xbn = x < rem ? q + 1 : q;                                    // and its block count
+  const uint32_t wpb = BLOCK / kWave;
+  // The XCD's share of the ray slots is [xs, xe); its W waves take
+  // kPacket-slot packets of it in turn (wave wx: packets wx, wx + W, wx + 2W, ...), so the
+  // waves of an XCD move through the share together and the rays in flight
+  // on it at any time are a window of consecutive slots.
+  const uint32_t W = xbn * wpb, wx = j * wpb + threadIdx.x / kWave;
+  const uint32_t xs = (uint32_t)(((uint64_t)xb0 * wpb * n) / waves);
+  const uint32_t xe = (uint32_t)(((uint64_t)(xb0 + xbn) * wpb * n) / waves);
+  // slot of this wave's v-th ray (monotonic in v)
+  auto slot_of = [&](uint32_t v) -> uint64_t {
+    return (uint64_t)xs + ((uint64_t)(v / kPacket) * W + wx) * kPacket + (v % kPacket);
+  };
+  uint32_t next = 0;  // rays this wave has taken
   int32_t* lstack = s_stack + threadIdx.x;
 
   Ray R{};
@@ -166,14 +177,16 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
   unsigned long long st_trips = 0, st_wave = 0, st_inner = 0, st_leaf = 0, st_tri = 0, st_rays = 0;
 
   while (true) {
-    // ---- refill idle lanes from the chunk (wave-uniform decision)
+    // ---- refill idle lanes from the wave's packets (wave-uniform decision)
     const uint64_t idle = __ballot(slot < 0);
     const uint32_t n_idle = (uint32_t)__popcll(idle);
-    if (n_idle == kWave && next >= end) break;
-    if (next < end && (n_idle >= refill || n_idle == kWave)) {
+    const bool more = slot_of(next) < xe;
+    if (n_idle == kWave && !more) break;
+    if (more && (n_idle >= refill || n_idle == kWave)) {
       if (slot < 0) {
-        const uint32_t s = next + lanes_below(idle);
-        if (s < end) {
+        const uint64_t s64 = slot_of(next + lanes_below(idle));
+        if (s64 < xe) {
+          const uint32_t s = (uint32_t)s64;
           slot = (int32_t)s;
           const uint32_t r = idx ? idx[s] : s;
           if (r < n_max) {
@@ -198,7 +211,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
           if (STATS) ++st_rays;
         }
       }
-      next = next + n_idle < end ? next + n_idle : end;
+      next += n_idle;
     }
     // counts one wave iteration per wave (by the lowest active lane)
     auto wave_tick = [&]() {
