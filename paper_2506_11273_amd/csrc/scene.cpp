@@ -182,7 +182,6 @@ void quantize_node(const Box* kids, int m, const int32_t* code, float4* out) {
   Box P;
   for (int j = 0; j < m; ++j) P.grow(kids[j]);
   float p[3], s[3];
-  uint32_t ebits = 0;
   // The trace kernel places plane q at the exact real p + q * 2^e (it never
   // rounds that sum), so the checks below bound the exact sum: D = p + q * s
   // in double is within 2^-53 |D| of it, and a margin of 2^-52 |D| makes
@@ -200,8 +199,7 @@ void quantize_node(const Box* kids, int m, const int32_t* code, float4* out) {
     }
     e = std::max(-100, e);
     while (!above((double)p[a] + std::ldexp(255.0, e), P.hi[a])) ++e;
-    s[a] = std::ldexp(1.0f, e);
-    ebits |= (uint32_t)(e + 127) << (8 * a);
+    s[a] = std::ldexp(1.0f, e);  // e >= -100: a normal binary32 power of two
   }
   auto dec = [&](int a, uint32_t q) { return (double)p[a] + (double)q * (double)s[a]; };
   uint32_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
@@ -226,9 +224,9 @@ void quantize_node(const Box* kids, int m, const int32_t* code, float4* out) {
     std::memcpy(&x, &v, 4);
     return x;
   };
-  out[0] = make_float4(p[0], p[1], p[2], f(ebits));
+  out[0] = make_float4(p[0], p[1], p[2], s[2]);
   out[1] = make_float4(f(lo[0]), f(hi[0]), f(lo[1]), f(hi[1]));
-  out[2] = make_float4(f(lo[2]), f(hi[2]), 0.0f, 0.0f);
+  out[2] = make_float4(f(lo[2]), f(hi[2]), s[0], s[1]);
   out[3] = make_float4(fi(code[0]), fi(code[1]), fi(code[2]), fi(code[3]));
 }
 

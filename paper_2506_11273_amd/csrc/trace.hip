@@ -16,10 +16,10 @@
 // Layout: a 4-wide inner node is either 8 x float4 = 128 bytes holding its
 // four child boxes in SoA form (lo.x[4], hi.x[4], lo.y[4], hi.y[4], lo.z[4],
 // hi.z[4], child[4], unused), or 4 x float4 = 64 bytes with the child bounds
-// quantised to 8 bits against the node box: (p.xyz, step exponents),
-// (lo.x, hi.x, lo.y, hi.y as 4 bytes each), (lo.z, hi.z, -, -), child[4];
-// a bound decodes to the exact p + q * 2^e, codes chosen by the builder so
-// that these planes enclose the child box.  A child
+// quantised to 8 bits against the node box: (p.xyz, s.z),
+// (lo.x, hi.x, lo.y, hi.y as 4 bytes each), (lo.z, hi.z, s.x, s.y), child[4],
+// with power-of-two steps s; a bound decodes to the exact p + q * s, codes
+// chosen by the builder so that these planes enclose the child box.  A child
 // >= 0 is an inner node, kEmptyChild an unused slot, and a child < 0 a leaf
 // ~(first << 3 | count) of at most 7 triangles (the builder makes at most 3).
 // A triangle is 3 x float4 = 48 bytes: (v0, e1.x), (e1.yz, e2.xy),
@@ -69,6 +69,7 @@ struct Ray {
   float ox, oy, oz, tmin;
   float dx, dy, dz, tmax;
   float ix, iy, iz;
+  float ax, ay, az;  // |inv| * 2^-20 per axis (exact scalings)
 };
 
 // Slab test of one child box; *tn receives the entry distance.
@@ -90,23 +91,24 @@ __device__ __forceinline__ bool slab(float lx, float hx, float ly, float hy, flo
 // per plane.  Which of the node's two code words holds the near planes
 // depends only on the sign of inv, so the caller passes the words in
 // near/far order.  Every plane is moved outward by
-// eps = |delta| 2^-20 + s 2^-12 (the near planes toward the ray, the far
-// planes away from it: near base (delta*inv - eps*|inv|), far base
-// (delta*inv + eps*|inv|)).  The rounding of delta, of delta*inv, of
-// eps*|inv|, of the bases, of s*inv and of the final fused multiply-add is
-// below (|delta| + 128 s) |inv| 2^-22, a quarter of the move, so the
+// ei = (|delta| 2^-20 + s 2^-12) |inv| (the near planes toward the ray, the
+// far planes away from it: near base delta*inv - ei, far base
+// delta*inv + ei), computed as fma(|delta|, |inv| 2^-20, |s*inv| 2^-12)
+// with exact power-of-two scalings, so it falls short of that value by at
+// most a factor 1 - 2^-22.  The rounding of delta, of delta*inv, of the
+// bases, of s*inv and of the final fused multiply-add is below
+// (|delta| + 128 s) |inv| 2^-22, about a quarter of the move, so the
 // computed slab contains the slab of the decoded box, which contains the
 // child's box.  (Coordinates are below 1e18 and steps below 2^61, so
 // nothing overflows.)
-__device__ __forceinline__ void qaxis(float p, float s, float o, float inv, uint32_t wnear, uint32_t wfar,
-                                      float (&tn)[4], float (&tf)[4]) {
+__device__ __forceinline__ void qaxis(float p, float s, float o, float inv, float ainv20, uint32_t wnear,
+                                      uint32_t wfar, float (&tn)[4], float (&tf)[4]) {
   const float delta = p - o;
-  const float eps = __builtin_fmaf(fabsf(delta), 0x1p-20f, s * 0x1p-12f);
+  const float step = s * inv;
+  const float ei = __builtin_fmaf(fabsf(delta), ainv20, fabsf(step) * 0x1p-12f);
   const float di = delta * inv;
-  const float ei = eps * fabsf(inv);
   const float nb = di - ei;
   const float fb = di + ei;
-  const float step = s * inv;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     tn[j] = __builtin_fmaf((float)((wnear >> (8 * j)) & 0xFFu), step, nb);
@@ -197,6 +199,9 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
             R.ix = 1.0f / nudge(b.x);
             R.iy = 1.0f / nudge(b.y);
             R.iz = 1.0f / nudge(b.z);
+            R.ax = fabsf(R.ix) * 0x1p-20f;
+            R.ay = fabsf(R.iy) * 0x1p-20f;
+            R.az = fabsf(R.iz) * 0x1p-20f;
             tbest = b.w;
             node = root;
           } else {
@@ -247,16 +252,12 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
         const float4* N = nodes + 4 * (size_t)node;
         const float4 a = N[0], b = N[1], c = N[2];
         cc = *reinterpret_cast<const int4*>(N + 3);
-        const uint32_t eb = __float_as_uint(a.w);
         const uint32_t xl = __float_as_uint(b.x), xh = __float_as_uint(b.y);
         const uint32_t yl = __float_as_uint(b.z), yh = __float_as_uint(b.w);
         const uint32_t zl = __float_as_uint(c.x), zh = __float_as_uint(c.y);
-        qaxis(a.x, __uint_as_float((eb & 0xFFu) << 23), R.ox, R.ix, R.ix < 0.0f ? xh : xl, R.ix < 0.0f ? xl : xh,
-              lox, hix);
-        qaxis(a.y, __uint_as_float(((eb >> 8) & 0xFFu) << 23), R.oy, R.iy, R.iy < 0.0f ? yh : yl,
-              R.iy < 0.0f ? yl : yh, loy, hiy);
-        qaxis(a.z, __uint_as_float(((eb >> 16) & 0xFFu) << 23), R.oz, R.iz, R.iz < 0.0f ? zh : zl,
-              R.iz < 0.0f ? zl : zh, loz, hiz);
+        qaxis(a.x, c.z, R.ox, R.ix, R.ax, R.ix < 0.0f ? xh : xl, R.ix < 0.0f ? xl : xh, lox, hix);
+        qaxis(a.y, c.w, R.oy, R.iy, R.ay, R.iy < 0.0f ? yh : yl, R.iy < 0.0f ? yl : yh, loy, hiy);
+        qaxis(a.z, a.w, R.oz, R.iz, R.az, R.iz < 0.0f ? zh : zl, R.iz < 0.0f ? zl : zh, loz, hiz);
         h0 = qslab(lox[0], hix[0], loy[0], hiy[0], loz[0], hiz[0], R.tmin, tbest, &t0) && cc.x != kEmptyChild;
         h1 = qslab(lox[1], hix[1], loy[1], hiy[1], loz[1], hiz[1], R.tmin, tbest, &t1) && cc.y != kEmptyChild;
         h2 = qslab(lox[2], hix[2], loy[2], hiy[2], loz[2], hiz[2], R.tmin, tbest, &t2) && cc.z != kEmptyChild;
