@@ -216,7 +216,7 @@ def main():
                     "tri_tests": round(prof["tri_tests"] / n, 2)},
         "hits_scatter_back_equal_unsorted": same,
         "roofline": trace_roofline(trace_bytes, trace_ms, n, profiled_traffic(args.key, args.builder),
-                                   profiled_valu(args.key, args.builder)),
+                                   profiled_valu(args.key, args.builder), prof["inner_visits"], prof["tri_tests"]),
     }
     if "variants" not in args.skip:
         result["variants"] = variants(torch, rr, scene, rays, n, lo, hi, dev, stream, args.steps, unsorted_ms, uhits)
@@ -285,22 +285,32 @@ def profiled_valu(key: str, builder: int):
         return None
 
 
-# VALU issue capacity without packed FP32: 256 CUs x 4 SIMDs, one wave64
-# instruction per SIMD every 4 cycles, 2.4 GHz.
-VALU_WAVE_INSTR_PER_S = 256 * 4 / 4 * 2.4e9
+# FP32 operations (add, mul, min/max and compare count 1, fused multiply-add
+# 2) of one quantised inner-node test (4 children: 72 for the three axes'
+# plane distances, 36 for the slab tests, 5 compares to order the hits) and
+# of one triangle test (the full Moller-Trumbore test with its range checks).
+FLOPS_PER_INNER_VISIT = 113
+FLOPS_PER_TRI_TEST = 54
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
-def trace_roofline(trace_bytes, trace_ms, n, traffic, valu_instr):
+def trace_roofline(trace_bytes, trace_ms, n, traffic, valu_instr, inner_visits=None, tri_tests=None):
     r = {"kernel": "k_trace4 (sorted rays)", "bound": "hbm",
          "achieved": round(trace_bytes / (trace_ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
          "frac": round(trace_bytes / (trace_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
          "traffic": traffic, "algorithmic_bytes_per_launch": trace_bytes, "algorithmic_bytes_per_ray": 48,
          "launch_ms": round(trace_ms, 4)}
-    # what actually bounds it: VALU issue (counted instructions over the
-    # issue capacity in the live launch time)
+    # VALU wave instructions per launch (SQ_INSTS_VALU of the committed
+    # counter run) and per ray: the kernel is bound by instruction issue,
+    # not by HBM
     r["valu_wave_instructions"] = valu_instr
-    r["valu_issue_frac"] = (round(valu_instr / (trace_ms * 1e-3) / VALU_WAVE_INSTR_PER_S, 3)
-                            if valu_instr else None)
+    r["valu_wave_instructions_per_ray"] = round(valu_instr / n, 1) if valu_instr else None
+    if inner_visits is not None:
+        flops = FLOPS_PER_INNER_VISIT * inner_visits + FLOPS_PER_TRI_TEST * tri_tests
+        tf = flops / (trace_ms * 1e-3) / 1e12
+        r["alu_view"] = {"flops_per_launch": int(flops), "flops_per_ray": round(flops / n, 1),
+                         "achieved_tflops": round(tf, 2), "peak_tflops": FP32_VECTOR_PEAK_TFLOPS,
+                         "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4)}
     return r
 
 
