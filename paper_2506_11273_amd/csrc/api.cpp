@@ -244,7 +244,7 @@ rr_status rr_sort_ex(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* c
 
 rr_status rr_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                   void* workspace, size_t ws_bytes, void* stream) {
-  return rr_sort_ex(keys, idx, n_max, count_dev, key_bits, 8, 16, workspace, ws_bytes, stream);
+  return rr_sort_ex(keys, idx, n_max, count_dev, key_bits, 8, kSortDefaultKpt, workspace, ws_bytes, stream);
 }
 
 rr_status rr_local_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
@@ -408,7 +408,7 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
     if ((r = launch_keys(rays, n, alive, plan, keys, idx, cnt, w + L.kscratch, st)) != RR_OK) return r;
     if (local_block) {
       if ((r = launch_local_sort(keys, idx, n, cnt, kb, local_block, st)) != RR_OK) return r;
-    } else if ((r = launch_sort(keys, idx, n, cnt, kb, 8, 16, w + L.sortws, L.sort_bytes, st)) != RR_OK) {
+    } else if ((r = launch_sort(keys, idx, n, cnt, kb, 8, kSortDefaultKpt, w + L.sortws, L.sort_bytes, st)) != RR_OK) {
       return r;
     }
   } else {

@@ -254,7 +254,7 @@ rr_status stage(rr_batch b, const rr_segment* segs, int32_t nseg, uint32_t flags
     total += g.n;
   }
   if (total > b->cap) return RR_ERR_BUDGET;
-  const uint32_t tile = 256u * c.keys_per_thread;
+  const uint32_t tile = sort_tile_keys(c.keys_per_thread);
   BatchHdr H{(uint32_t)nseg, (uint32_t)total, 0u, 0u};
   BatchSeg* bs = reinterpret_cast<BatchSeg*>(h + b->off_segs);
   SortSeg* ss = reinterpret_cast<SortSeg*>(h + b->off_ssegs);

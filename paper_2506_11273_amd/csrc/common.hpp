@@ -18,7 +18,7 @@ constexpr int kMaxTreeDepth = 32;      // binary BVH leaf depth cap (the builder
 // never deeper than the binary node it was collapsed from.
 constexpr int kTraceStack4 = 3 * kMaxTreeDepth;
 constexpr int32_t kEmptyChild = 0x7FFFFFFF;  // unused child slot of a 4-wide node
-constexpr uint32_t kDefaultRefill = 16;      // idle lanes that trigger a wave refill
+constexpr uint32_t kDefaultRefill = 8;       // idle lanes that trigger a wave refill
 constexpr uint32_t kStatusCountMask = 0x3FFFFFFFu;
 constexpr uint32_t kStatusAggregate = 1u << 30;
 constexpr uint32_t kStatusPrefix = 2u << 30;
@@ -85,6 +85,9 @@ rr_status launch_local_sort(void* keys, uint32_t* idx, int64_t n_max, const uint
 
 // --------------------------------------------------------------- sort
 size_t sort_workspace_bytes(int64_t n_max, uint32_t key_bits, uint32_t digit_bits, uint32_t kpt);
+// Keys of one sort tile for kpt keys per thread (the sort's block size times kpt).
+uint32_t sort_tile_keys(uint32_t kpt);
+constexpr uint32_t kSortDefaultKpt = 8;  // keys per thread of rr_sort and the fused call
 size_t sort_workspace_bytes_any(int64_t n_max, uint32_t key_bits);
 bool sort_config_supported(uint32_t key_bits, uint32_t digit_bits, uint32_t kpt);
 rr_status launch_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,

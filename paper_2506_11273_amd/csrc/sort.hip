@@ -42,7 +42,7 @@
 namespace rr {
 namespace {
 
-constexpr int kSortThreads = 256;
+constexpr int kSortThreads = 512;
 constexpr int kSortWaves = kSortThreads / kWave;
 constexpr uint32_t kGroup = 8;           // tiles per look-back group
 constexpr uint32_t kTileWindow = kGroup - 1;  // tile words read per look-back round
@@ -598,6 +598,8 @@ SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_
   L.total = off;
   return L;
 }
+
+uint32_t sort_tile_keys(uint32_t kpt) { return kSortThreads * kpt; }
 
 bool sort_config_supported(uint32_t key_bits, uint32_t digit_bits, uint32_t kpt) {
   return (key_bits == 32 || key_bits == 64) && (digit_bits == 4 || digit_bits == 8) && (kpt == 8 || kpt == 16);

@@ -329,7 +329,7 @@ def rr_compute_keys(rays, params: KeyParams, alive=None, keys=None, idx=None, co
     return keys, idx, count
 
 
-def rr_sort(keys, idx, count=None, key_bits: Optional[int] = None, digit_bits: int = 8, keys_per_thread: int = 16,
+def rr_sort(keys, idx, count=None, key_bits: Optional[int] = None, digit_bits: int = 8, keys_per_thread: int = 8,
             ws=None, stream=None):
     """Stable in-place sort of (keys, idx)."""
     torch = _torch()
