@@ -230,6 +230,32 @@ def test_trace_small_city_matches_oracle(rr):
         assert_hits_match(h, ref, w.rays, w.tris, f"city builder {builder}")
 
 
+def test_trace_ragged_counts_and_refill(rr, soup65k):
+    """Ray counts around the 64-ray packets and the XCD shares of the
+    persistent waves (fewer blocks than XCDs, ragged last packets), a device
+    count below the capacity (slots past it untouched), and several refill
+    thresholds: the same hits every time."""
+    w = soup65k
+    N = 30011
+    rays = np.ascontiguousarray(w.rays[:N])
+    ref = O.brute_force(w.tris, rays)
+    with rr.Scene(w.tris, builder=1) as sc:
+        for n in (1, 63, 64, 65, 511, 2049, 4097, 12345, N):
+            h = rr.hits_to_numpy(rr.rr_trace(sc, to_dev(rays[:n])))
+            assert_hits_match(h, ref[:n], rays[:n], w.tris, f"n={n}")
+        dr = to_dev(rays)
+        full = rr.rr_trace(sc, dr)
+        cnt = torch.tensor([7777], dtype=torch.int32, device=DEV)
+        out = torch.full((N, 4), -3.0, dtype=torch.float32, device=DEV)
+        rr.rr_trace(sc, dr, count=cnt, hits=out)
+        assert torch.equal(out[:7777].view(torch.int32), full[:7777].view(torch.int32))
+        assert bool((out[7777:] == -3.0).all())
+        for refill in (1, 8, 33, 64):
+            h = rr.rr_trace(sc, dr, refill=refill)
+            assert torch.equal(h.view(torch.int32), full.view(torch.int32)), f"refill {refill}"
+    assert_hits_match(rr.hits_to_numpy(full), ref, rays, w.tris, "full")
+
+
 def test_trace_tiny_scenes_and_ties(rr):
     # one triangle (the root is a leaf); shared-edge tie goes to the lower id
     a = [1, 0, 0.5, 0, 1, 0.5, 1, 1, 0.5]
