@@ -5,7 +5,7 @@
 // (Section 1), so the builder is a free choice.  Two are provided:
 //  * median split: split at the median centroid along the widest centroid
 //    axis; balanced, depth ceil(log2(ceil(n/4))), fast to build;
-//  * binned SAH: 32 bins per axis on centroids, surface-area cost, falling
+//  * binned SAH: 256 bins per axis on centroids, surface-area cost, falling
 //    back to the median split when a subtree could otherwise exceed the
 //    trace kernel's stack depth.
 // Leaves hold at most 3 triangles.  Nodes are emitted in depth-first order
@@ -25,7 +25,7 @@ namespace rr {
 namespace {
 
 constexpr int kLeafMax = 3;  // measured best of 2..6 and SAH-terminated leaves of up to 7
-constexpr int kBins = 32;
+constexpr int kBins = 256;
 
 struct Box {
   float lo[3] = {INFINITY, INFINITY, INFINITY};
