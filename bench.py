@@ -144,6 +144,14 @@ def main():
         rr.rr_trace(scene, rays, hits=uhits)
         if ev: ev[1].record(stream)
 
+    # the headline step: one fused call (keys, the sort with the ray gather in
+    # its last pass, the trace), hits in key order
+    fhits = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    fws = rr.workspace(rr.reorder_workspace_size(n, params), dev)
+
+    def fused():
+        rr.rr_reorder_and_trace(scene, rays, params, flags=0, hits=fhits, ws=fws, want_perm=False, want_count=False)
+
     if args.phases == "trace":
         for _ in range(args.warmup):
             step()
@@ -159,27 +167,34 @@ def main():
         return
 
     for _ in range(args.warmup):
+        fused()
         step()
         unsorted()
     torch.cuda.synchronize()
 
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k])
+        fused()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
 
+    # the same work as separate calls, for the per-phase times
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
     phase = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(4)] for k in range(args.steps)])
     keys_ms, sort_ms, gather_ms, trace_ms = np.median(phase, axis=0)
     unsorted_ms = median_ms(torch, stream, unsorted, args.steps)
 
-    # what was timed is correct: the sorted hits scattered back equal the unsorted hits
+    # what was timed is correct: the fused call's hits equal the separate
+    # calls' hits, and scattered back they equal the unsorted trace's hits
+    same_fused = bool(torch.equal(fhits.view(torch.int32), hits.view(torch.int32)))
     back = rr.rr_scatter_hits(hits, idx)
     torch.cuda.synchronize()
-    same = bool(torch.equal(back.view(torch.int32), uhits.view(torch.int32)))
+    same = bool(torch.equal(back.view(torch.int32), uhits.view(torch.int32))) and same_fused
     prof = rr.rr_trace_profile(scene, srays)
     uprof = rr.rr_trace_profile(scene, rays)
 
@@ -202,12 +217,14 @@ def main():
         "config": {"workload": "bounce2_diffuse_1920x1080_grid_city_1M_tris", "rays": int(n),
                    "triangles": int(w.tris.shape[0]), "key": args.key, "term_ratio": 0.25,
                    "bvh": ["median", "sah"][args.builder] + " collapsed to 4-wide",
-                   "step": "keys+sort+gather+trace, hits in key order"},
+                   "step": "rr_reorder_and_trace: keys, sort (ray gather fused into its last pass), trace; "
+                           "hits in key order"},
         "unsorted_trace_mrays": round(n / (unsorted_ms * 1e-3) / 1e6, 2),
         "trace_speedup_sorted_vs_unsorted": round(unsorted_ms / trace_ms, 3),
         "reorder_vs_unsorted": round(unsorted_ms / ms_per_step, 3),
         "phase_ms": {"keys": round(keys_ms, 4), "sort": round(sort_ms, 4), "gather": round(gather_ms, 4),
-                     "trace_sorted": round(trace_ms, 4), "trace_unsorted": round(unsorted_ms, 4)},
+                     "trace_sorted": round(trace_ms, 4), "trace_unsorted": round(unsorted_ms, 4),
+                     "separate_calls_total": round(keys_ms + sort_ms + gather_ms + trace_ms, 4)},
         "sort_gbs": round(sort_bytes / (sort_ms * 1e-3) / 1e9, 1),
         "sort_roofline_frac": round(sort_bytes / (sort_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
         "simd_efficiency": {"sorted": round(prof["simd_efficiency"], 3),
@@ -215,6 +232,7 @@ def main():
         "per_ray": {"inner_visits": round(prof["inner_visits"] / n, 2), "leaf_visits": round(prof["leaf_visits"] / n, 2),
                     "tri_tests": round(prof["tri_tests"] / n, 2)},
         "hits_scatter_back_equal_unsorted": same,
+        "fused_hits_equal_separate_calls": same_fused,
         "roofline": trace_roofline(trace_bytes, trace_ms, n, profiled_traffic(args.key, args.builder),
                                    profiled_valu(args.key, args.builder), prof["inner_visits"], prof["tri_tests"]),
     }
@@ -324,13 +342,13 @@ def variants(torch, rr, scene, rays, n, lo, hi, dev, stream, steps, unsorted_ms,
     hits."""
     out = {}
     hits = torch.empty((n, 4), dtype=torch.float32, device=dev)
-    cnt = torch.empty(1, dtype=torch.int32, device=dev)
     for name, (kind, bits) in KEYS.items():
         p = rr.key_params(kind, bits, lo, hi, 0.25)
         ws = rr.workspace(rr.reorder_workspace_size(n, p), dev)
         for flags, tag in ((0, ""), (rr.RR_HITS_ORIGINAL_ORDER, "_scatter_back"), (rr.RR_INDIRECT, "_indirect")):
             def run():
-                rr.rr_reorder_and_trace(scene, rays, p, flags=flags, hits=hits, count=cnt, ws=ws, want_perm=False)
+                rr.rr_reorder_and_trace(scene, rays, p, flags=flags, hits=hits, ws=ws, want_perm=False,
+                                        want_count=False)
             run(); run()
             ms = median_ms(torch, stream, run, steps)
             out[name + tag] = {"ms": round(ms, 4), "mrays": round(n / (ms * 1e-3) / 1e6, 2),
@@ -344,7 +362,7 @@ def variants(torch, rr, scene, rays, n, lo, hi, dev, stream, steps, unsorted_ms,
         for flag, block in ((rr.RR_LOCAL_SORT_1024, 1024), (rr.RR_LOCAL_SORT_2048, 2048),
                             (rr.RR_LOCAL_SORT_4096, 4096)):
             def run():
-                rr.rr_reorder_and_trace(scene, rays, p, flags=flag, hits=hits, count=cnt, ws=ws, want_perm=False)
+                rr.rr_reorder_and_trace(scene, rays, p, flags=flag, hits=hits, ws=ws, want_perm=False, want_count=False)
             run(); run()
             ms = median_ms(torch, stream, run, steps)
             k, idx, _ = rr.rr_compute_keys(rays, p)
@@ -361,7 +379,7 @@ def variants(torch, rr, scene, rays, n, lo, hi, dev, stream, steps, unsorted_ms,
         p = rr.key_params(kind, bits, lo, hi, 0.25, aux=aux)
         ws = rr.workspace(rr.reorder_workspace_size(n, p), dev)
         def run():
-            rr.rr_reorder_and_trace(scene, rays, p, flags=0, hits=hits, count=cnt, ws=ws, want_perm=False)
+            rr.rr_reorder_and_trace(scene, rays, p, flags=0, hits=hits, ws=ws, want_perm=False, want_count=False)
         run(); run()
         ms = median_ms(torch, stream, run, steps)
         # the trace alone on this method's order

@@ -404,10 +404,17 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
     return RR_OK;
   }
 
+  bool gathered = false;  // srays already hold the rays in key order
   if (sorted) {
     if ((r = launch_keys(rays, n, alive, plan, keys, idx, cnt, w + L.kscratch, st)) != RR_OK) return r;
     if (local_block) {
       if ((r = launch_local_sort(keys, idx, n, cnt, kb, local_block, st)) != RR_OK) return r;
+    } else if (!indirect) {
+      // the device-wide sort's last pass also gathers the rays
+      if ((r = launch_sort_gather(keys, idx, n, cnt, kb, 8, kSortDefaultKpt, w + L.sortws, L.sort_bytes, rays, srays,
+                                  st)) != RR_OK)
+        return r;
+      gathered = true;
     } else if ((r = launch_sort(keys, idx, n, cnt, kb, 8, kSortDefaultKpt, w + L.sortws, L.sort_bytes, st)) != RR_OK) {
       return r;
     }
@@ -419,7 +426,7 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
   if (indirect) {
     if ((r = trace(s->d, rays, idx, n, cnt, tout, st)) != RR_OK) return r;
   } else {
-    if ((r = launch_gather(rays, idx, n, cnt, srays, st)) != RR_OK) return r;
+    if (!gathered && (r = launch_gather(rays, idx, n, cnt, srays, st)) != RR_OK) return r;
     if ((r = trace(s->d, srays, nullptr, n, cnt, tout, st)) != RR_OK) return r;
   }
   if (plan.kind == RR_KEY_TWO_POINT_ADAPTIVE) {

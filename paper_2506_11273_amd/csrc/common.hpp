@@ -92,6 +92,12 @@ size_t sort_workspace_bytes_any(int64_t n_max, uint32_t key_bits);
 bool sort_config_supported(uint32_t key_bits, uint32_t digit_bits, uint32_t kpt);
 rr_status launch_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                       uint32_t digit_bits, uint32_t kpt, void* ws, size_t ws_bytes, hipStream_t st);
+// The same sort with the ray gather fused into its last pass:
+// rays_out[i] = rays_in[idx[i]] for the sorted indices (n_max rays in); the
+// keys are left unsorted.
+rr_status launch_sort_gather(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                             uint32_t digit_bits, uint32_t kpt, void* ws, size_t ws_bytes, const rr_ray* rays_in,
+                             rr_ray* rays_out, hipStream_t st);
 
 // ------------------------------------------------------ gather / scatter
 rr_status launch_gather(const rr_ray* in, const uint32_t* idx, int64_t n_max, const uint32_t* count_dev, rr_ray* out,

@@ -339,7 +339,9 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
                                                            uint32_t copies, const uint32_t* __restrict__ hist,
                                                            uint32_t* __restrict__ status,
                                                            uint32_t* __restrict__ gstatus,
-                                                           uint32_t* tile_counter) {
+                                                           uint32_t* tile_counter,
+                                                           const float4* __restrict__ gather_in,
+                                                           float4* __restrict__ gather_out, uint32_t gather_n) {
   using S = PassSmem<K, DB, KPT>;
   constexpr uint32_t R = S::R;
   constexpr uint32_t kTile = S::kTile;
@@ -489,8 +491,21 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
       const uint32_t d = (uint32_t)(key >> shift) & (R - 1);
       const uint32_t out = sm.delta[d] + p;
       if (out < seg_end) {  // always true when the histograms are consistent
-        keys_out[out] = key;
-        idx_out[out] = sm.idx[p];
+        const uint32_t v = sm.idx[p];
+        if (keys_out) keys_out[out] = key;
+        idx_out[out] = v;
+        if (gather_out) {
+          // the gather fused into the last pass: the record of ray v moves to
+          // its sorted slot (an index outside the rays yields a NaN record)
+          const float nan = __int_as_float(0x7fc00000);
+          float4 a = make_float4(nan, nan, nan, nan), b = a;
+          if (v < gather_n) {
+            a = gather_in[2 * (size_t)v];
+            b = gather_in[2 * (size_t)v + 1];
+          }
+          gather_out[2 * (size_t)out] = a;
+          gather_out[2 * (size_t)out + 1] = b;
+        }
       }
     }
     tile = next;
@@ -523,7 +538,8 @@ struct Resident {
 
 template <typename K, int DB, int KPT>
 rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, SortHdr* hdr_ext, SortSeg* segs_ext,
-                        const uint32_t* count_dev, uint32_t n_max, bool counted, hipStream_t st) {
+                        const uint32_t* count_dev, uint32_t n_max, bool counted, const rr_ray* gather_in,
+                        rr_ray* gather_out, uint32_t gather_n, hipStream_t st) {
   constexpr uint32_t R = 1u << DB;
   K* kalt = reinterpret_cast<K*>(ws + L.keys_alt);
   uint32_t* ialt = reinterpret_cast<uint32_t*>(ws + L.idx_alt);
@@ -558,10 +574,13 @@ rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, So
   K* dst_k = kalt;
   uint32_t* dst_i = ialt;
   for (uint32_t p = 0; p < L.passes; ++p) {
-    hipLaunchKernelGGL((k_seg_pass<K, DB, KPT>), dim3(pass_blocks), dim3(kSortThreads), 0, st, src_k, src_i, dst_k,
-                       dst_i, hdr, segs, p * DB, L.passes, p, L.hist_copies, hist,
-                       status + (size_t)p * L.status_stride,
-                       gstatus + (size_t)p * L.gstatus_stride, counted ? counters + p : nullptr);
+    // the last pass of a sort with a fused gather writes the rays instead of the keys
+    const bool g = gather_out && p + 1 == L.passes;
+    hipLaunchKernelGGL((k_seg_pass<K, DB, KPT>), dim3(pass_blocks), dim3(kSortThreads), 0, st, src_k, src_i,
+                       g ? nullptr : dst_k, dst_i, hdr, segs, p * DB, L.passes, p, L.hist_copies, hist,
+                       status + (size_t)p * L.status_stride, gstatus + (size_t)p * L.gstatus_stride,
+                       counted ? counters + p : nullptr, g ? reinterpret_cast<const float4*>(gather_in) : nullptr,
+                       g ? reinterpret_cast<float4*>(gather_out) : nullptr, gather_n);
     std::swap(src_k, dst_k);
     std::swap(src_i, dst_i);
   }
@@ -635,12 +654,13 @@ void sort_warm(uint32_t key_bits, uint32_t db, uint32_t kpt) {
 
 rr_status launch_seg_sort(void* keys, uint32_t* idx, const SegLayout& L, void* ws, SortHdr* hdr, SortSeg* segs,
                           const uint32_t* count_dev, uint32_t n_max, uint32_t key_bits, uint32_t db, uint32_t kpt,
-                          bool counted, hipStream_t st) {
+                          bool counted, hipStream_t st, const rr_ray* gather_in, rr_ray* gather_out,
+                          uint32_t gather_n) {
   char* w = reinterpret_cast<char*>(ws);
 #define RR_SORT_CASE(KT, DBV, KPTV)                                                                        \
   if (sizeof(KT) * 8 == key_bits && db == DBV && kpt == KPTV)                                            \
     return seg_sort_impl<KT, DBV, KPTV>(reinterpret_cast<KT*>(keys), idx, L, w, hdr, segs, count_dev, n_max, counted, \
-                                        st);
+                                        gather_in, gather_out, gather_n, st);
   RR_SORT_CASE(uint32_t, 8, 16)
   RR_SORT_CASE(uint32_t, 8, 8)
   RR_SORT_CASE(uint32_t, 4, 16)
@@ -660,6 +680,16 @@ rr_status launch_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* 
   if (ws_bytes < L.total) return RR_ERR_WORKSPACE_TOO_SMALL;
   return launch_seg_sort(keys, idx, L, ws, nullptr, nullptr, count_dev, (uint32_t)n_max, key_bits, db, kpt, false,
                          st);
+}
+
+rr_status launch_sort_gather(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                             uint32_t db, uint32_t kpt, void* ws, size_t ws_bytes, const rr_ray* rays_in,
+                             rr_ray* rays_out, hipStream_t st) {
+  if (!sort_config_supported(key_bits, db, kpt)) return RR_ERR_UNSUPPORTED;
+  const SegLayout L = seg_layout(n_max, 1, key_bits, db, kpt);
+  if (ws_bytes < L.total) return RR_ERR_WORKSPACE_TOO_SMALL;
+  return launch_seg_sort(keys, idx, L, ws, nullptr, nullptr, count_dev, (uint32_t)n_max, key_bits, db, kpt, false,
+                         st, rays_in, rays_out, (uint32_t)n_max);
 }
 
 }  // namespace rr

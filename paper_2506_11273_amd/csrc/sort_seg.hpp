@@ -31,9 +31,13 @@ SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_
 // keys (n_max without count_dev) is set up on the device, in the workspace.
 // counted: the scatter passes take tiles from a counter (for sorts that may
 // share the device with other kernels) instead of in a fixed order.
+// gather_out: the last pass also moves the rays into sorted order,
+// gather_out[i] = gather_in[idx[i]] (gather_n rays in), and leaves the keys
+// of that pass unwritten.
 rr_status launch_seg_sort(void* keys, uint32_t* idx, const SegLayout& L, void* ws, SortHdr* hdr, SortSeg* segs,
                           const uint32_t* count_dev, uint32_t n_max, uint32_t key_bits, uint32_t db, uint32_t kpt,
-                          bool counted, hipStream_t st);
+                          bool counted, hipStream_t st, const rr_ray* gather_in = nullptr,
+                          rr_ray* gather_out = nullptr, uint32_t gather_n = 0);
 
 // Runs the one-time occupancy queries of a sort configuration, so that a
 // later stream capture records kernel launches only.

@@ -419,15 +419,17 @@ def rr_trace_profile(scene: Scene, rays, hits=None, stream=None) -> dict:
 
 
 def rr_reorder_and_trace(scene: Scene, rays, params: KeyParams, alive=None, flags: int = RR_HITS_ORIGINAL_ORDER,
-                         hits=None, perm=None, count=None, ws=None, want_perm: bool = True, stream=None):
-    """Keys, sort, gather and trace in one call.  Returns (hits, perm, count)."""
+                         hits=None, perm=None, count=None, ws=None, want_perm: bool = True, want_count: bool = True,
+                         stream=None):
+    """Keys, sort, gather and trace in one call.  Returns (hits, perm, count);
+    perm and count are None when not given and not wanted."""
     torch = _torch()
     L = load()
     n = _n_rows(rays)
     hits = torch.empty((n, 4), dtype=torch.float32, device=rays.device) if hits is None else hits
     if perm is None and want_perm:
         perm = _empty(n, torch.int32, rays.device)
-    if count is None:
+    if count is None and want_count:
         count = _empty(1, torch.int32, rays.device)
     if ws is None:
         ws = workspace(reorder_workspace_size(n, params), rays.device)
