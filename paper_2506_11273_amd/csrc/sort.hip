@@ -348,6 +348,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
   __shared__ S sm;
   const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const uint32_t nseg = hdr->nseg, T = hdr->total_tiles;
+  const SortSeg seg0 = segs[0];  // loaded beside the header: a single sort needs no other
   uint32_t cur = 0xFFFFFFFFu;  // segment whose digit bases are in sm.base
 
   for (uint32_t i = tid; i < kSortWaves * R; i += kSortThreads) (&sm.wave_hist[0][0])[i] = 0;
@@ -379,8 +380,8 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
   uint32_t s = 0;
   SortSeg sg{};
   if (tile < T) {
-    s = seg_of_tile(segs, nseg, tile);
-    sg = segs[s];
+    s = nseg == 1 ? 0u : seg_of_tile(segs, nseg, tile);
+    sg = nseg == 1 ? seg0 : segs[s];
     const uint32_t lt = tile - sg.tile_off;
     load_tile(sg.off + lt * kTile, min(kTile, sg.n - lt * kTile));
   }
@@ -480,8 +481,8 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
     // ---- prefetch the next tile, then write this one's digit runs
     const uint32_t seg_end = sg.off + sg.n;
     const uint32_t next = counted ? sm.ticket : tile + gridDim.x;
-    const uint32_t s_next = next < T ? seg_of_tile(segs, nseg, next) : s;
-    const SortSeg sg_next = next < T ? segs[s_next] : sg;
+    const uint32_t s_next = next < T && nseg != 1 ? seg_of_tile(segs, nseg, next) : s;
+    const SortSeg sg_next = next < T && nseg != 1 ? segs[s_next] : sg;
     if (next < T) {
       const uint32_t lt_next = next - sg_next.tile_off;
       load_tile(sg_next.off + lt_next * kTile, min(kTile, sg_next.n - lt_next * kTile));
