@@ -296,7 +296,8 @@ rr_status rr_trace_profile(rr_scene s, const rr_ray* rays, int64_t n, rr_hit* hi
 
 /* --------------------------------------------------------- fused pipeline
  * Keys (with compaction when `alive` is given), sort, gather and trace on
- * one stream: the reordered trace of Section 3.2 / Section 4.4.1.
+ * one stream: the reordered trace of Section 3.2 / Section 4.4.1.  With the
+ * device-wide sort, the gather is done by the sort's last pass.
  *  hits      device, n entries.  With RR_HITS_ORIGINAL_ORDER, hits[i] is the
  *            hit of rays[i] and dead slots receive a miss record; otherwise
  *            hits[i] belongs to the i-th ray in key order and entries past

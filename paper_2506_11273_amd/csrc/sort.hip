@@ -7,22 +7,26 @@
 //    device (a compaction count, a batch table) and one captured launch
 //    sequence serves any mix;
 //  * k_seg_hist reads every key once and builds the digit histograms of all
-//    passes per segment;
-//  * k_seg_pass blocks are persistent.  A sort that has the device to
-//    itself takes tiles in a fixed order (block b: tiles b, b + G, ...), so
-//    no shared tile counter is contended; the batched layer, whose sorts may
-//    share the device with other kernels, takes them in order from an atomic
-//    counter, so that a tile is only ever held by a running block (each
-//    block takes its next ticket while it works on the current tile).  A tile is ranked by digit with wave64 ballots (a match over
-//    the digit's bits gives each lane its peers; the lowest peer bumps the
-//    wave's digit counter in LDS), its digit counts are published, the
-//    previous tiles of the same segment are looked back for the global
-//    offsets (decoupled look-back, Merrill and Garland 2016), and the tile is
-//    reordered in LDS and written as contiguous digit runs.
+//    passes per segment (a single sort spreads them over one copy per XCD,
+//    so that few atomics meet on one device word);
+//  * k_seg_pass blocks (512 threads) are persistent.  A sort that has the
+//    device to itself takes tiles in a fixed order (block b: tiles b,
+//    b + G, ...), so no shared tile counter is contended; the batched layer,
+//    whose sorts may share the device with other kernels, takes them in order
+//    from an atomic counter, so that a tile is only ever held by a running
+//    block (each block takes its next ticket while it works on the current
+//    tile).  A tile is ranked by digit with wave64 ballots (a match over the
+//    digit's bits gives each lane its peers; the lowest peer adds the group's
+//    size to the wave's digit count with one LDS atomic), its digit counts
+//    are published, the previous tiles of the same segment are looked back
+//    for the global offsets (decoupled look-back, Merrill and Garland 2016),
+//    and the tile is reordered in LDS and written as contiguous digit runs
+//    (the last pass of the fused call also moves the rays to their slots).
 //  * The look-back is two-level: tiles form groups of kGroup, and the last
 //    tile of a group also publishes the group's total and then its inclusive
 //    prefix, so a tile reads its own group's tiles and then whole groups,
-//    kGroup tiles per word.
+//    kGroup tiles per word.  Every round reads its whole window for each
+//    digit, past the L2, so the windows are kept small.
 //  * Waits never depend on other blocks being resident: an entry that stays
 //    unpublished for a bounded number of polls is computed by the waiting
 //    thread itself from the input keys (the fallback of decoupled look-back,
@@ -49,12 +53,12 @@ constexpr uint32_t kTileWindow = kGroup - 1;  // tile words read per look-back r
 constexpr uint32_t kGroupWindow = kGroup;     // group words read per look-back round
 constexpr uint32_t kFallbackSpins = 128;       // polls of an unpublished entry before computing it
 constexpr uint32_t kFallbackSpinsCounted = 1u << 16;  // tiles from the counter: waiting is always safe
-constexpr uint32_t kHistUnit = 4096;  // keys per histogram work unit (16 per thread)
+constexpr uint32_t kHistUnit = 4096;  // keys per histogram work unit (8 per thread)
 constexpr uint32_t kHistCopies = 8;   // histogram copies of a single-segment sort (one per XCD)
 
-// Exclusive scan of one value per thread over a 256-thread block (wave
-// shuffles, then the four wave totals); s needs kSortWaves words.
-__device__ __forceinline__ uint32_t block_scan_256(uint32_t v, uint32_t* s, uint32_t* total) {
+// Exclusive scan of one value per thread over the block (wave shuffles,
+// then the kSortWaves wave totals); s needs kSortWaves words.
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* s, uint32_t* total) {
   const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   uint32_t x = v;
 #pragma unroll
@@ -418,7 +422,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
       uint32_t h = 0;
       if (tid < R)
         for (uint32_t c = 0; c < copies; ++c) h += hist[(((size_t)s * copies + c) * passes + pass) * R + tid];
-      const uint32_t ex = block_scan_256(h, sm.scan, &total);
+      const uint32_t ex = block_scan(h, sm.scan, &total);
       if (tid < R) sm.base[tid] = sg.off + ex;
       cur = s;
     }
@@ -439,7 +443,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
       store_status(&status[(size_t)tile * R + d], (lt == 0 ? kStatusPrefix : kStatusAggregate) | c);
     }
     uint32_t total;
-    const uint32_t local = block_scan_256(count, sm.scan, &total);
+    const uint32_t local = block_scan(count, sm.scan, &total);
     if (tid < R) {
 #pragma unroll
       for (int w = 0; w < kSortWaves; ++w) sm.wave_hist[w][tid] = local + wpre[w];

@@ -25,10 +25,12 @@
 // A triangle is 3 x float4 = 48 bytes: (v0, e1.x), (e1.yz, e2.xy),
 // (e2.z, prim id bits, -, -), with e1 = v1 - v0 and e2 = v2 - v0.
 //
-// Execution: persistent wavefronts.  Wave w owns a contiguous chunk of the
-// rays (in key order when the rays were reordered) and refills its idle
-// lanes from that chunk whenever at least `refill` lanes are idle, so lanes
-// whose rays finish early do not idle until the wave's longest ray ends.
+// Execution: persistent wavefronts.  Each XCD owns a contiguous share of
+// the ray slots (in key order when the rays were reordered); its waves take
+// 64-slot packets of that share in turn, and a wave refills its idle lanes
+// from its packets whenever at least `refill` lanes are idle, so lanes whose
+// rays finish early do not idle until the wave's longest ray ends, and the
+// rays in flight on an XCD stay a window of neighbouring slots.
 // The traversal stack holds at most 3 entries per tree level; its first
 // kLdsStack entries live in LDS (interleaved by lane), the rest in scratch.
 #include <algorithm>
