@@ -46,7 +46,7 @@ TRAFFIC_PROFILE = os.path.join("profiles", "k_trace4_bounce2_1080p_traffic.txt")
 TRAFFIC_SOURCES = ("paper_2506_11273_amd/csrc/trace.hip", "paper_2506_11273_amd/csrc/scene.cpp",
                    "paper_2506_11273_amd/csrc/common.hpp", "paper_2506_11273_amd/csrc/keys_dev.hpp",
                    "paper_2506_11273_amd/csrc/keys.hip", "workloads/gen.c")
-SECTIONS = ("variants", "orders", "shadow", "bounce3", "sorts", "batch", "serve", "cpu")
+SECTIONS = ("variants", "orders", "shuffled", "shadow", "bounce3", "sorts", "batch", "serve", "cpu")
 
 
 def parse():
@@ -240,6 +240,8 @@ def main():
         result["variants"] = variants(torch, rr, scene, rays, n, lo, hi, dev, stream, args.steps, unsorted_ms, uhits)
     if "orders" not in args.skip:
         result["coherence"] = orders(torch, rr, scene, rays, n, lo, hi, dev, stream, args.steps, uhits)
+    if "shuffled" not in args.skip:
+        result["shuffled_input"] = shuffled_input(torch, rr, W, scene, rays, n, dev, stream, args.steps)
     if "shadow" not in args.skip:
         result["shadow_1080p"] = shadow(torch, rr, W, scene, dev, stream, args.steps)
     if "bounce3" not in args.skip:
@@ -432,6 +434,47 @@ def orders(torch, rr, scene, rays, n, lo, hi, dev, stream, steps, uhits):
     a = np.array([v["rel_trace"] for v in out.values()])
     b = np.array([v["rel_m64"] for v in out.values()])
     return {"orders": out, "pearson_rel_trace_vs_rel_m64": round(float(np.corrcoef(a, b)[0, 1]), 3)}
+
+
+def shuffled_input(torch, rr, W, scene, rays, n, dev, stream, steps):
+    """Rays that arrive in an incoherent order (a seeded random permutation
+    of the wavefront): their trace against the fused reorder-and-trace call
+    on the same input, which sorts them first.  On the headline wavefront
+    and on first-bounce rays at 3840x2160 in the 4M-triangle city."""
+    def study(sc, r, nrays):
+        lo, hi = sc.bounds()
+        perm = torch.from_numpy(np.random.default_rng(7).permutation(nrays)).to(dev)
+        sh = r.index_select(0, perm).contiguous()
+        hits = torch.empty((nrays, 4), dtype=torch.float32, device=dev)
+        t_pixel = median_ms(torch, stream, lambda: rr.rr_trace(sc, r, hits=hits), steps)
+        t_sh = median_ms(torch, stream, lambda: rr.rr_trace(sc, sh, hits=hits), steps)
+        out = {"rays": int(nrays), "trace_generation_order_ms": round(t_pixel, 4),
+               "trace_shuffled_ms": round(t_sh, 4), "fused_from_shuffled": {}}
+        for name in ("od32", "origin", "ot64"):
+            kind, bits = METHODS[name] if name in METHODS else KEYS[name]
+            p = rr.key_params(kind, bits, lo, hi, 0.25)
+            ws = rr.workspace(rr.reorder_workspace_size(nrays, p), dev)
+
+            def run():
+                rr.rr_reorder_and_trace(sc, sh, p, flags=0, hits=hits, ws=ws, want_perm=False, want_count=False)
+            run()
+            ms = median_ms(torch, stream, run, steps)
+            out["fused_from_shuffled"][name] = {"ms": round(ms, 4), "vs_shuffled_trace": round(t_sh / ms, 3)}
+            del ws
+        del sh, hits
+        return out
+
+    res = {"city1M_bounce2_1080p": study(scene, rays, n)}
+    c = W.city(5, 200, 200, 3_520_000)
+    with rr.Scene(c.tris) as sc4:
+        r = W.camera_rays(5, 3840, 2160, (100.0, 120.0, 100.0))
+        r, alive = W.bounce(c, 5, 300, r, np.ones(r.shape[0], np.uint8))
+        r = np.ascontiguousarray(r[alive.astype(bool)])
+        rd = torch.from_numpy(r).to(dev)
+        res["city4M_bounce1_2160p"] = study(sc4, rd, r.shape[0])
+        del rd
+    torch.cuda.empty_cache()
+    return res
 
 
 def shadow(torch, rr, W, scene, dev, stream, steps):
