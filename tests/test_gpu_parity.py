@@ -315,6 +315,49 @@ def test_reorder_and_trace_with_compaction(rr):
             assert np.all(h["prim"][~live] == -1) and np.all(np.isinf(h["t"][~live]))
 
 
+def test_reorder_and_trace_compaction_edges_every_flag(rr, soup65k):
+    """Live sets at the edges (none, only the first slot, only the last slot,
+    every other slot, all) through the fused call with the gather in the
+    sort's last pass, the gather kernel (local sort) and the indirect trace,
+    hits in key order and in ray order: the live hits equal the plain trace,
+    the key-order hits follow the permutation, and the count is exact."""
+    w = soup65k
+    n = 5003
+    rays_np = np.ascontiguousarray(w.rays[:n])
+    lo, hi = O.scene_box(w.tris)
+    masks = {"none": np.zeros(n, np.uint8), "first": np.eye(1, n, 0, dtype=np.uint8)[0],
+             "last": np.eye(1, n, n - 1, dtype=np.uint8)[0], "alternate": (np.arange(n) % 2).astype(np.uint8),
+             "all": np.ones(n, np.uint8)}
+    with rr.Scene(w.tris) as sc:
+        rays = to_dev(rays_np)
+        full = rr.hits_to_numpy(rr.rr_trace(sc, rays))
+        for kind, bits in [(O.KIND_OD, 32), (O.KIND_OT, 64)]:
+            p = rr.key_params(kind, bits, lo, hi)
+            for mname, m in masks.items():
+                live = np.nonzero(m)[0]
+                ref_idx = live.astype(np.uint32)
+                if len(live):
+                    cidx = O.compact(m)
+                    _, ref_idx = O.sort_pairs(O.keys(rays_np[cidx], kind, bits, lo, hi), cidx)
+                for flags in (0, rr.RR_HITS_ORIGINAL_ORDER, rr.RR_INDIRECT, rr.RR_LOCAL_SORT_2048):
+                    what = f"kind {kind}/{bits} mask {mname} flags {flags}"
+                    hits, perm, cnt = rr.rr_reorder_and_trace(sc, rays, p, alive=to_dev(m), flags=flags)
+                    c = int(cnt.cpu().numpy()[0])
+                    assert c == len(live), what
+                    pi = idx_np(perm)[:c]
+                    if flags & rr.RR_LOCAL_SORT_2048:
+                        assert np.array_equal(np.sort(pi), live), what
+                    else:
+                        assert np.array_equal(pi, ref_idx), what
+                    h = rr.hits_to_numpy(hits)
+                    if flags & rr.RR_HITS_ORIGINAL_ORDER:
+                        assert h[live].tobytes() == full[live].tobytes(), what
+                        dead = m == 0
+                        assert np.all(h["prim"][dead] == -1) and np.all(np.isinf(h["t"][dead])), what
+                    else:
+                        assert h[:c].tobytes() == full[pi].tobytes(), what
+
+
 def test_zero_rays(rr, soup65k):
     w = soup65k
     with rr.Scene(w.tris[:10]) as sc:
