@@ -15,7 +15,6 @@
 #include <cmath>
 #include <cstring>
 #include <future>
-#include <limits>
 #include <memory>
 #include <new>
 #include <vector>
@@ -59,12 +58,6 @@ struct BNode {
   Box box;
   std::unique_ptr<BNode> kid[2];
   int32_t first = 0, count = 0;  // leaf range in the builder's index array
-  // 4-wide collapse: cost[k] of covering this subtree's top with k children
-  // (k = 1: this node as one child), split[k] the share of them taken from
-  // kid[0], best the number of children this node gets as a 4-wide node
-  double cost[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  uint8_t split[5] = {0, 0, 0, 0, 0};
-  uint8_t best = 0;
 };
 
 int median_depth(int64_t n) {
@@ -177,55 +170,9 @@ struct Builder {
   }
 };
 
-// Surface-area costs of collapsing the binary tree to 4 wide, by a dynamic
-// program over the tree: a subtree top may be covered by k = 1..4 nodes of
-// the frontier below it, and a node kept as one child costs its area plus
-// its own best cover by 2..4 children (the surface-area heuristic: a node is
-// visited with a probability proportional to its area), so the program
-// minimises the expected number of 4-wide node visits.  The leaves are those
-// of the binary tree in every cover, so their cost is the same for all and
-// is left out.  Only ratios of areas matter, so there is no normalisation.
-void collapse_costs(BNode* n) {
-  const double inf = std::numeric_limits<double>::infinity();
-  if (!n->kid[0]) {
-    n->cost[1] = 0.0;
-    n->cost[2] = n->cost[3] = n->cost[4] = inf;
-    return;
-  }
-  BNode* a = n->kid[0].get();
-  BNode* b = n->kid[1].get();
-  collapse_costs(a);
-  collapse_costs(b);
-  double best = inf;
-  for (int k = 2; k <= 4; ++k) {
-    n->cost[k] = inf;
-    for (int k1 = 1; k1 < k; ++k1) {
-      const double v = a->cost[k1] + b->cost[k - k1];
-      if (v < n->cost[k]) {
-        n->cost[k] = v;
-        n->split[k] = (uint8_t)k1;
-      }
-    }
-    if (n->cost[k] < best) {
-      best = n->cost[k];
-      n->best = (uint8_t)k;
-    }
-  }
-  n->cost[1] = n->box.area() + best;
-}
-
-// The k frontier nodes that cover n's subtree top in the cheapest way.
-void frontier(const BNode* n, int k, const BNode** out, int* m) {
-  if (k == 1) {
-    out[(*m)++] = n;
-    return;
-  }
-  frontier(n->kid[0].get(), n->split[k], out, m);
-  frontier(n->kid[1].get(), k - n->split[k], out, m);
-}
-
-// Emits the 4-wide BVH: each binary inner node becomes a node whose children
-// are its cheapest cover by 2..4 frontier nodes (collapse_costs).
+// Emits the 4-wide BVH: each binary inner node is widened by repeatedly
+// replacing its largest-area inner child with that child's two children
+// until it has four children or only leaves remain.
 // 8-bit quantised child bounds (compressed 64-byte node): per axis an
 // origin p (the node's lower bound) and a power-of-two step s with
 // 255 * s >= extent; a child bound is stored as q, the plane at the exact
@@ -310,9 +257,21 @@ struct Packer {
   int32_t pack(const BNode* n, int depth) {
     max_depth = std::max(max_depth, depth);
     if (!n->kid[0]) return leaf(n);
-    const BNode* kids[4] = {nullptr, nullptr, nullptr, nullptr};
-    int m = 0;
-    frontier(n, n->best, kids, &m);
+    const BNode* kids[4] = {n->kid[0].get(), n->kid[1].get(), nullptr, nullptr};
+    int m = 2;
+    while (m < 4) {
+      int best = -1;
+      double best_area = -1.0;
+      for (int j = 0; j < m; ++j)
+        if (kids[j]->kid[0] && kids[j]->box.area() > best_area) {
+          best = j;
+          best_area = kids[j]->box.area();
+        }
+      if (best < 0) break;
+      const BNode* x = kids[best];
+      kids[best] = x->kid[0].get();
+      kids[m++] = x->kid[1].get();
+    }
     const int32_t me = (int32_t)(nodes.size() / stride);
     nodes.resize(nodes.size() + stride);
     int32_t code[4] = {kEmptyChild, kEmptyChild, kEmptyChild, kEmptyChild};
@@ -360,7 +319,6 @@ rr_status build_scene(const float* tris, int64_t n, int builder, DeviceScene* ou
   for (int64_t i = 0; i < n; ++i) order[(size_t)i] = (int32_t)i;
   Builder B(prims, order, builder);
   std::unique_ptr<BNode> root = B.build(0, n, 0);
-  collapse_costs(root.get());
   Packer P{tris, order, {}, {}, 0, quantised ? 4 : 8};
   P.nodes.reserve((size_t)(n / 4 + 8) * P.stride);
   P.gtris.reserve((size_t)n * 3);
