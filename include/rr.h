@@ -230,7 +230,8 @@ rr_status rr_sort_workspace_size(int64_t n_max, uint32_t key_bits, size_t* bytes
 rr_status rr_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                   void* workspace, size_t ws_bytes, void* stream);
 /* Same, with an explicit radix digit width (4 or 8 bits) and keys per
- * thread (tile size); every choice gives the identical result. */
+ * thread (tile size); every choice gives the identical result.  rr_sort uses
+ * 8-bit digits and 8 keys per thread, 16 from 2^24 keys (n_max) on. */
 rr_status rr_sort_ex(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                      uint32_t digit_bits, uint32_t keys_per_thread, void* workspace, size_t ws_bytes,
                      void* stream);

@@ -244,7 +244,8 @@ rr_status rr_sort_ex(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* c
 
 rr_status rr_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                   void* workspace, size_t ws_bytes, void* stream) {
-  return rr_sort_ex(keys, idx, n_max, count_dev, key_bits, 8, kSortDefaultKpt, workspace, ws_bytes, stream);
+  return rr_sort_ex(keys, idx, n_max, count_dev, key_bits, 8, sort_default_kpt(n_max), workspace, ws_bytes,
+                    stream);
 }
 
 rr_status rr_local_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
@@ -411,11 +412,11 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
       if ((r = launch_local_sort(keys, idx, n, cnt, kb, local_block, st)) != RR_OK) return r;
     } else if (!indirect) {
       // the device-wide sort's last pass also gathers the rays
-      if ((r = launch_sort_gather(keys, idx, n, cnt, kb, 8, kSortDefaultKpt, w + L.sortws, L.sort_bytes, rays, srays,
+      if ((r = launch_sort_gather(keys, idx, n, cnt, kb, 8, sort_default_kpt(n), w + L.sortws, L.sort_bytes, rays, srays,
                                   st)) != RR_OK)
         return r;
       gathered = true;
-    } else if ((r = launch_sort(keys, idx, n, cnt, kb, 8, kSortDefaultKpt, w + L.sortws, L.sort_bytes, st)) != RR_OK) {
+    } else if ((r = launch_sort(keys, idx, n, cnt, kb, 8, sort_default_kpt(n), w + L.sortws, L.sort_bytes, st)) != RR_OK) {
       return r;
     }
   } else {

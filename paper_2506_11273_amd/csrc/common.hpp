@@ -87,7 +87,10 @@ rr_status launch_local_sort(void* keys, uint32_t* idx, int64_t n_max, const uint
 size_t sort_workspace_bytes(int64_t n_max, uint32_t key_bits, uint32_t digit_bits, uint32_t kpt);
 // Keys of one sort tile for kpt keys per thread (the sort's block size times kpt).
 uint32_t sort_tile_keys(uint32_t kpt);
-constexpr uint32_t kSortDefaultKpt = 8;  // keys per thread of rr_sort and the fused call
+// Keys per thread of rr_sort and the fused call for n keys: 8 (tiles of 4096
+// keys) up to 2^24 keys, 16 (tiles of 8192, fewer tiles to look back over)
+// beyond.
+uint32_t sort_default_kpt(int64_t n);
 size_t sort_workspace_bytes_any(int64_t n_max, uint32_t key_bits);
 bool sort_config_supported(uint32_t key_bits, uint32_t digit_bits, uint32_t kpt);
 rr_status launch_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,

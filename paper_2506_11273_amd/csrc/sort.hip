@@ -625,6 +625,8 @@ SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_
 
 uint32_t sort_tile_keys(uint32_t kpt) { return kSortThreads * kpt; }
 
+uint32_t sort_default_kpt(int64_t n) { return n >= (int64_t(1) << 24) ? 16u : 8u; }
+
 bool sort_config_supported(uint32_t key_bits, uint32_t digit_bits, uint32_t kpt) {
   return (key_bits == 32 || key_bits == 64) && (digit_bits == 4 || digit_bits == 8) && (kpt == 8 || kpt == 16);
 }

@@ -329,18 +329,25 @@ def rr_compute_keys(rays, params: KeyParams, alive=None, keys=None, idx=None, co
     return keys, idx, count
 
 
-def rr_sort(keys, idx, count=None, key_bits: Optional[int] = None, digit_bits: int = 8, keys_per_thread: int = 8,
-            ws=None, stream=None):
-    """Stable in-place sort of (keys, idx)."""
+def rr_sort(keys, idx, count=None, key_bits: Optional[int] = None, digit_bits: int = 8,
+            keys_per_thread: Optional[int] = None, ws=None, stream=None):
+    """Stable in-place sort of (keys, idx); keys_per_thread None takes the
+    library's choice for the size (rr_sort), a value calls rr_sort_ex."""
     torch = _torch()
     L = load()
     n = int(keys.shape[0])
     kb = key_bits or (64 if keys.dtype == torch.int64 else 32)
     if ws is None:
         ws = workspace(sort_workspace_size(n, kb), keys.device)
-    _check(L.rr_sort_ex(_ptr(keys, "keys", (torch.int32, torch.int64)), _ptr(idx, "idx", torch.int32), n,
-                        _ptr(count, "count", torch.int32, False), kb, digit_bits, keys_per_thread,
-                        _ptr(ws, "workspace"), ws.numel() * ws.element_size(), _stream(stream)), "rr_sort")
+    kp = _ptr(keys, "keys", (torch.int32, torch.int64))
+    ip = _ptr(idx, "idx", torch.int32)
+    cp = _ptr(count, "count", torch.int32, False)
+    wp, wb = _ptr(ws, "workspace"), ws.numel() * ws.element_size()
+    if keys_per_thread is None and digit_bits == 8:
+        _check(L.rr_sort(kp, ip, n, cp, kb, wp, wb, _stream(stream)), "rr_sort")
+    else:
+        _check(L.rr_sort_ex(kp, ip, n, cp, kb, digit_bits, keys_per_thread or 8, wp, wb, _stream(stream)),
+               "rr_sort")
     return keys, idx
 
 
