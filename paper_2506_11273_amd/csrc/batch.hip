@@ -57,24 +57,45 @@ __device__ __forceinline__ uint32_t seg_of_pos(const BatchSeg* segs, uint32_t ns
   return lo;
 }
 
+// The same for positions that ascend with the lane (the streaming loops
+// below): one wave-uniform search from the first active lane's position,
+// then each lane steps over the few segment starts between it and its own.
+__device__ __forceinline__ uint32_t seg_of_pos_wave(const BatchSeg* segs, uint32_t nseg, uint32_t p) {
+  const uint32_t p0 = __builtin_amdgcn_readfirstlane(p);
+  uint32_t s = seg_of_pos(segs, nseg, p0);
+  if (p < p0) return seg_of_pos(segs, nseg, p);  // not taken: positions ascend with the lane
+  while (s + 1 < nseg && segs[s + 1].out_off <= p) ++s;
+  return s;
+}
+
+// Runs f(segment) with the segment index wave-uniform when every active
+// lane is in the same segment (so its descriptor is read with scalar
+// loads), else per lane.
+template <typename F>
+__device__ __forceinline__ void with_segment(const BatchSeg* segs, uint32_t s, F&& f) {
+  const uint32_t su = __builtin_amdgcn_readfirstlane(s);
+  if (__ballot(s != su) == 0) f(segs[su]);
+  else f(segs[s]);
+}
+
 template <typename K>
 __global__ __launch_bounds__(kBatchBlock) void k_batch_keys(const BatchHdr* __restrict__ hdr,
                                                             const BatchSeg* __restrict__ segs, K* __restrict__ keys,
                                                             uint32_t* __restrict__ idx) {
   const uint32_t total = hdr->total, nseg = hdr->nseg;
   for (uint32_t p = blockIdx.x * kBatchBlock + threadIdx.x; p < total; p += gridDim.x * kBatchBlock) {
-    const uint32_t s = seg_of_pos(segs, nseg, p);
-    const BatchSeg& S = segs[s];
-    const uint32_t r = p - S.out_off;
-    uint64_t key = 0;
-    if (S.plan.kind != 0) {
-      const float4 a = S.rays[2 * (size_t)r];
-      const float4 b = S.rays[2 * (size_t)r + 1];
-      key = ray_key_any(a, b, S.plan, r);
-      key <<= S.shift;
-    }
-    keys[p] = (K)key;
-    idx[p] = r;
+    with_segment(segs, seg_of_pos_wave(segs, nseg, p), [&](const BatchSeg& S) {
+      const uint32_t r = p - S.out_off;
+      uint64_t key = 0;
+      if (S.plan.kind != 0) {
+        const float4 a = S.rays[2 * (size_t)r];
+        const float4 b = S.rays[2 * (size_t)r + 1];
+        key = ray_key_any(a, b, S.plan, r);
+        key <<= S.shift;
+      }
+      keys[p] = (K)key;
+      idx[p] = r;
+    });
   }
 }
 
@@ -86,8 +107,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_gather(const BatchHdr* __
   const uint32_t total = hdr->total, nseg = hdr->nseg;
   for (uint32_t t = blockIdx.x * kBatchBlock + threadIdx.x; t < 2 * total; t += gridDim.x * kBatchBlock) {
     const uint32_t i = t >> 1, h = t & 1;
-    const uint32_t s = seg_of_pos(segs, nseg, i);
-    out[2 * (size_t)i + h] = segs[s].rays[2 * (size_t)idx[i] + h];
+    with_segment(segs, seg_of_pos_wave(segs, nseg, i),
+                 [&](const BatchSeg& S) { out[2 * (size_t)i + h] = S.rays[2 * (size_t)idx[i] + h]; });
   }
 }
 
@@ -97,11 +118,11 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_out(const BatchHdr* __res
                                                            const float4* __restrict__ hits_sorted) {
   const uint32_t total = hdr->total, nseg = hdr->nseg;
   for (uint32_t p = blockIdx.x * kBatchBlock + threadIdx.x; p < total; p += gridDim.x * kBatchBlock) {
-    const uint32_t s = seg_of_pos(segs, nseg, p);
-    const BatchSeg& S = segs[s];
-    const uint32_t r = idx[p], q = p - S.out_off;
-    S.hits[S.orig ? r : q] = hits_sorted[p];
-    if (S.perm) S.perm[q] = r;
+    with_segment(segs, seg_of_pos_wave(segs, nseg, p), [&](const BatchSeg& S) {
+      const uint32_t r = idx[p], q = p - S.out_off;
+      S.hits[S.orig ? r : q] = hits_sorted[p];
+      if (S.perm) S.perm[q] = r;
+    });
   }
 }
 
