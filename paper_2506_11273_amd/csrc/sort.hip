@@ -8,7 +8,9 @@
 //    sequence serves any mix;
 //  * k_seg_hist reads every key once and builds the digit histograms of all
 //    passes per segment (a single sort spreads them over one copy per XCD,
-//    so that few atomics meet on one device word);
+//    so that few atomics meet on one device word, and a block counts into
+//    eight LDS copies, so that lanes with equal digits seldom meet on one
+//    LDS word);
 //  * k_seg_pass blocks (512 threads) are persistent.  A sort that has the
 //    device to itself takes tiles in a fixed order (block b: tiles b,
 //    b + G, ...), so no shared tile counter is contended; the batched layer,
@@ -55,6 +57,8 @@ constexpr uint32_t kFallbackSpins = 128;       // polls of an unpublished entry 
 constexpr uint32_t kFallbackSpinsCounted = 1u << 16;  // tiles from the counter: waiting is always safe
 constexpr uint32_t kHistUnit = 4096;  // keys per histogram work unit (8 per thread)
 constexpr uint32_t kHistCopies = 8;   // histogram copies of a single-segment sort (one per XCD)
+constexpr uint32_t kHistLaneCopies = 8;  // LDS histogram copies per block, lane l counts into copy l % 8
+constexpr uint32_t kHistCopyPad = 8;     // words between LDS copies beyond their size: copy c starts 8c banks on
 
 // Exclusive scan of one value per thread over the block (wave shuffles,
 // then the kSortWaves wave totals); s needs kSortWaves words.
@@ -125,6 +129,11 @@ __global__ void k_seg_init(const SortHdr* hdr, uint32_t* __restrict__ hist, uint
 // XCDs in turn, so with 8 copies each copy takes the atomics of one XCD and
 // no device word takes more than about blocks / copies of them); the
 // look-back words (tile and group) the passes will use are cleared too.
+// Neighbouring rays of a coherent wavefront share their high digits, and the
+// LDS atomics of lanes that hit one word serialize: each lane therefore
+// counts into one of kHistLaneCopies copies (lane mod 8), laid out so that
+// the copies of a word sit in different banks, and the copies are summed at
+// the flush.
 template <typename K, int DB, int KPT>
 __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__ keys, const SortHdr* hdr,
                                                            const SortSeg* __restrict__ segs, uint32_t passes,
@@ -140,13 +149,25 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
   constexpr uint32_t kPer = kUnitKeys / kSortThreads;
   constexpr uint32_t kMaxPasses = (8 * sizeof(K) + DB - 1) / DB;
   static_assert(kHistUnit % kSortThreads == 0, "unit size");
-  __shared__ uint32_t s_h[kMaxPasses * R];
+  constexpr uint32_t kStride = kMaxPasses * R + kHistCopyPad;
+  __shared__ uint32_t s_h[kHistLaneCopies * kStride];
   const uint32_t nseg = hdr->nseg, T = hdr->total_tiles;
   const uint32_t U = T * kUnitsPerTile;
   const uint32_t words = passes * R;
   const uint32_t copy = blockIdx.x % copies;
-  for (uint32_t i = threadIdx.x; i < words; i += kSortThreads) s_h[i] = 0;
+  uint32_t* const lane_h = s_h + (threadIdx.x % kHistLaneCopies) * kStride;
+  for (uint32_t i = threadIdx.x; i < kHistLaneCopies * kStride; i += kSortThreads) s_h[i] = 0;
   __syncthreads();
+  // the count of word i over the lane copies, which are cleared for reuse
+  auto take = [&](uint32_t i) {
+    uint32_t v = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < kHistLaneCopies; ++c) {
+      v += s_h[c * kStride + i];
+      s_h[c * kStride + i] = 0;
+    }
+    return v;
+  };
   const uint32_t u0 = (uint32_t)(((uint64_t)blockIdx.x * U) / gridDim.x);
   const uint32_t u1 = (uint32_t)(((uint64_t)(blockIdx.x + 1) * U) / gridDim.x);
   uint32_t cur = u0 < u1 ? seg_of_tile(segs, nseg, u0 / kUnitsPerTile) : 0u;
@@ -157,8 +178,8 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
     if (s != cur) {
       __syncthreads();
       for (uint32_t i = threadIdx.x; i < words; i += kSortThreads) {
-        if (s_h[i]) atomicAdd(&hist[((size_t)cur * copies + copy) * words + i], s_h[i]);
-        s_h[i] = 0;
+        const uint32_t v = take(i);
+        if (v) atomicAdd(&hist[((size_t)cur * copies + copy) * words + i], v);
       }
       __syncthreads();
       cur = s;
@@ -176,13 +197,15 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
     for (uint32_t q = 0; q < kPer; ++q) {
       if (first + q * kSortThreads + threadIdx.x >= last) continue;
       for (uint32_t p = 0; p < passes; ++p)
-        atomicAdd(&s_h[p * R + ((uint32_t)(k[q] >> (p * DB)) & (R - 1))], 1u);
+        atomicAdd(&lane_h[p * R + ((uint32_t)(k[q] >> (p * DB)) & (R - 1))], 1u);
     }
   }
   __syncthreads();
   if (u0 < u1)
-    for (uint32_t i = threadIdx.x; i < words; i += kSortThreads)
-      if (s_h[i]) atomicAdd(&hist[((size_t)cur * copies + copy) * words + i], s_h[i]);
+    for (uint32_t i = threadIdx.x; i < words; i += kSortThreads) {
+      const uint32_t v = take(i);
+      if (v) atomicAdd(&hist[((size_t)cur * copies + copy) * words + i], v);
+    }
   // clear the look-back words of the tiles and groups this sort will use
   const uint32_t stride = gridDim.x * kSortThreads;
   const uint32_t groups = T / kGroup + nseg;
