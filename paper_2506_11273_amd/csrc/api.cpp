@@ -5,6 +5,7 @@
 #include <new>
 
 #include "common.hpp"
+#include "sort_seg.hpp"
 
 namespace rr {
 rr_status build_scene(const float* tris, int64_t n, int builder, DeviceScene* out);
@@ -406,7 +407,14 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
   }
 
   bool gathered = false;  // srays already hold the rays in key order
-  if (sorted) {
+  if (sorted && !alive && !local_block && !indirect) {
+    // dense device-wide sort: the keys kernel also counts the digits, and
+    // the sort's last pass gathers the rays
+    if ((r = launch_keys_sort_gather(rays, n, plan, keys, idx, sort_default_kpt(n), w + L.sortws, L.sort_bytes, srays,
+                                     st)) != RR_OK)
+      return r;
+    gathered = true;
+  } else if (sorted) {
     if ((r = launch_keys(rays, n, alive, plan, keys, idx, cnt, w + L.kscratch, st)) != RR_OK) return r;
     if (local_block) {
       if ((r = launch_local_sort(keys, idx, n, cnt, kb, local_block, st)) != RR_OK) return r;

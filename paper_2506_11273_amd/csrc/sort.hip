@@ -42,6 +42,7 @@
 #include <utility>
 
 #include "common.hpp"
+#include "keys_dev.hpp"
 #include "sort_seg.hpp"
 #include "wave.hpp"
 
@@ -213,6 +214,69 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
     for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < T * R; i += stride)
       status[(size_t)p * status_pass_stride + i] = 0;
     for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < groups * R; i += stride)
+      gstatus[(size_t)p * gstatus_pass_stride + i] = 0;
+  }
+}
+
+// The keys of a dense single-segment sort computed and counted in one pass
+// (the fused reorder-and-trace call): block b takes a contiguous run of
+// kHistUnit-ray units, computes each ray's key exactly as the keys kernel
+// does (key and identity index written out), counts the 8-bit digits of
+// every pass into the lane copies in LDS and flushes them into histogram
+// copy b % copies like k_seg_hist, and clears the look-back words of
+// status_tiles tiles and status_groups groups per pass.  The histogram
+// copies must have been cleared before.
+template <int KIND, typename K>
+__global__ __launch_bounds__(kSortThreads) void k_keys_hist(const float4* __restrict__ rays, uint32_t n,
+                                                            KeyPlan P, K* __restrict__ keys,
+                                                            uint32_t* __restrict__ idx, uint32_t passes,
+                                                            uint32_t copies, uint32_t* __restrict__ hist,
+                                                            uint32_t* __restrict__ status,
+                                                            uint32_t status_pass_stride, uint32_t status_tiles,
+                                                            uint32_t* __restrict__ gstatus,
+                                                            uint32_t gstatus_pass_stride, uint32_t status_groups) {
+  constexpr int DB = 8;
+  constexpr uint32_t R = 1u << DB;
+  constexpr uint32_t kPer = kHistUnit / kSortThreads;
+  constexpr uint32_t kMaxPasses = 8 * sizeof(K) / DB;
+  constexpr uint32_t kStride = kMaxPasses * R + kHistCopyPad;
+  __shared__ uint32_t s_h[kHistLaneCopies * kStride];
+  const uint32_t words = passes * R;
+  const uint32_t copy = blockIdx.x % copies;
+  uint32_t* const lane_h = s_h + (threadIdx.x % kHistLaneCopies) * kStride;
+  for (uint32_t i = threadIdx.x; i < kHistLaneCopies * kStride; i += kSortThreads) s_h[i] = 0;
+  __syncthreads();
+  const uint32_t U = (n + kHistUnit - 1) / kHistUnit;
+  const uint32_t u0 = (uint32_t)(((uint64_t)blockIdx.x * U) / gridDim.x);
+  const uint32_t u1 = (uint32_t)(((uint64_t)(blockIdx.x + 1) * U) / gridDim.x);
+  for (uint32_t u = u0; u < u1; ++u) {
+    const uint32_t first = u * kHistUnit;
+#pragma unroll
+    for (uint32_t q = 0; q < kPer; ++q) {
+      const uint32_t i = first + q * kSortThreads + threadIdx.x;
+      if (i >= n) continue;
+      const float4 a = rays[2 * (size_t)i];
+      const float4 b = rays[2 * (size_t)i + 1];
+      const K k = (K)ray_key<KIND>(a, b, P, i);
+      keys[i] = k;
+      idx[i] = i;
+      for (uint32_t p = 0; p < passes; ++p)
+        atomicAdd(&lane_h[p * R + ((uint32_t)(k >> (p * DB)) & (R - 1))], 1u);
+    }
+  }
+  __syncthreads();
+  if (u0 < u1)
+    for (uint32_t i = threadIdx.x; i < words; i += kSortThreads) {
+      uint32_t v = 0;
+#pragma unroll
+      for (uint32_t c = 0; c < kHistLaneCopies; ++c) v += s_h[c * kStride + i];
+      if (v) atomicAdd(&hist[(size_t)copy * words + i], v);
+    }
+  const uint32_t stride = gridDim.x * kSortThreads;
+  for (uint32_t p = 0; p < passes; ++p) {
+    for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < status_tiles * R; i += stride)
+      status[(size_t)p * status_pass_stride + i] = 0;
+    for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < status_groups * R; i += stride)
       gstatus[(size_t)p * gstatus_pass_stride + i] = 0;
   }
 }
@@ -564,10 +628,39 @@ struct Resident {
   }
 };
 
+template <int KIND, typename K>
+uint32_t keys_hist_resident() {
+  static const uint32_t v = resident(k_keys_hist<KIND, K>, kSortThreads);
+  return v;
+}
+
+// Launches k_keys_hist for the key family of P (8-bit digits).
+template <typename K>
+void launch_keys_hist(const KeyPlan& P, uint32_t units, const float4* rays, uint32_t n, K* keys, uint32_t* idx,
+                      uint32_t passes, uint32_t copies, uint32_t* hist, uint32_t* status, uint32_t status_stride,
+                      uint32_t tiles, uint32_t* gstatus, uint32_t gstatus_stride, uint32_t groups, hipStream_t st) {
+#define RR_KEYS_HIST(F)                                                                                           \
+  hipLaunchKernelGGL((k_keys_hist<F, K>), dim3(std::max(1u, std::min(units, std::min(keys_hist_resident<F, K>(), \
+                                                                                       1024u)))),              \
+                     dim3(kSortThreads), 0, st, rays, n, P, keys, idx, passes, copies, hist, status, status_stride, \
+                     tiles, gstatus, gstatus_stride, groups)
+  const int f = key_family(P.kind);
+  if (f == 1) RR_KEYS_HIST(1);
+  else if (f == 2) RR_KEYS_HIST(2);
+  else if constexpr (sizeof(K) == 4) RR_KEYS_HIST(3);
+#undef RR_KEYS_HIST
+}
+
+// A dense single-segment sort whose keys k_keys_hist computes from rays.
+struct KeySource {
+  const rr_ray* rays;
+  KeyPlan plan;
+};
+
 template <typename K, int DB, int KPT>
 rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, SortHdr* hdr_ext, SortSeg* segs_ext,
                         const uint32_t* count_dev, uint32_t n_max, bool counted, const rr_ray* gather_in,
-                        rr_ray* gather_out, uint32_t gather_n, hipStream_t st) {
+                        rr_ray* gather_out, uint32_t gather_n, hipStream_t st, const KeySource* ksrc = nullptr) {
   constexpr uint32_t R = 1u << DB;
   K* kalt = reinterpret_cast<K*>(ws + L.keys_alt);
   uint32_t* ialt = reinterpret_cast<uint32_t*>(ws + L.idx_alt);
@@ -591,10 +684,19 @@ rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, So
                        hist_words, counters, L.passes);
   // about one unit per block: each block flushes its whole histogram with
   // global atomics, so more blocks than units only adds flush traffic
-  const uint32_t hist_units = std::max(1u, max_tiles * L.tile / kHistUnit);
-  const uint32_t hist_blocks = std::max(1u, std::min(hist_units, std::min(hist_res, 1024u)));
-  hipLaunchKernelGGL((k_seg_hist<K, DB, KPT>), dim3(hist_blocks), dim3(kSortThreads), 0, st, keys, hdr, segs,
-                     L.passes, L.hist_copies, hist, status, L.status_stride, gstatus, L.gstatus_stride);
+  if (ksrc) {
+    // keys from the rays, counted in the same kernel (n_max keys, no device count)
+    const uint32_t tiles = (n_max + L.tile - 1) / L.tile;
+    if constexpr (DB == 8)
+      launch_keys_hist<K>(ksrc->plan, (n_max + kHistUnit - 1) / kHistUnit,
+                          reinterpret_cast<const float4*>(ksrc->rays), n_max, keys, idx, L.passes, L.hist_copies, hist,
+                          status, L.status_stride, tiles, gstatus, L.gstatus_stride, tiles / kGroup + 1, st);
+  } else {
+    const uint32_t hist_units = std::max(1u, max_tiles * L.tile / kHistUnit);
+    const uint32_t hist_blocks = std::max(1u, std::min(hist_units, std::min(hist_res, 1024u)));
+    hipLaunchKernelGGL((k_seg_hist<K, DB, KPT>), dim3(hist_blocks), dim3(kSortThreads), 0, st, keys, hdr, segs,
+                       L.passes, L.hist_copies, hist, status, L.status_stride, gstatus, L.gstatus_stride);
+  }
   // one resident wave of blocks
   const uint32_t pass_blocks = std::max(1u, std::min(max_tiles, pass_res));
   K* src_k = keys;
@@ -710,6 +812,28 @@ rr_status launch_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* 
   if (ws_bytes < L.total) return RR_ERR_WORKSPACE_TOO_SMALL;
   return launch_seg_sort(keys, idx, L, ws, nullptr, nullptr, count_dev, (uint32_t)n_max, key_bits, db, kpt, false,
                          st);
+}
+
+rr_status launch_keys_sort_gather(const rr_ray* rays, int64_t n, const KeyPlan& plan, void* keys, uint32_t* idx,
+                                  uint32_t kpt, void* ws, size_t ws_bytes, rr_ray* rays_out, hipStream_t st) {
+  const uint32_t key_bits = plan.key64 ? 64u : 32u;
+  if (n <= 0) return RR_OK;
+  if (!sort_config_supported(key_bits, 8, kpt) || (plan.key64 && key_family(plan.kind) == 3))
+    return RR_ERR_UNSUPPORTED;
+  const SegLayout L = seg_layout(n, 1, key_bits, 8, kpt);
+  if (ws_bytes < L.total) return RR_ERR_WORKSPACE_TOO_SMALL;
+  const KeySource src{rays, plan};
+  char* w = reinterpret_cast<char*>(ws);
+#define RR_KSORT_CASE(KT, KPTV)                                                                              \
+  if (sizeof(KT) * 8 == key_bits && kpt == KPTV)                                                           \
+    return seg_sort_impl<KT, 8, KPTV>(reinterpret_cast<KT*>(keys), idx, L, w, nullptr, nullptr, nullptr,   \
+                                      (uint32_t)n, false, rays, rays_out, (uint32_t)n, st, &src);
+  RR_KSORT_CASE(uint32_t, 16)
+  RR_KSORT_CASE(uint32_t, 8)
+  RR_KSORT_CASE(uint64_t, 16)
+  RR_KSORT_CASE(uint64_t, 8)
+#undef RR_KSORT_CASE
+  return RR_ERR_UNSUPPORTED;
 }
 
 rr_status launch_sort_gather(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,

@@ -39,6 +39,15 @@ rr_status launch_seg_sort(void* keys, uint32_t* idx, const SegLayout& L, void* w
                           bool counted, hipStream_t st, const rr_ray* gather_in = nullptr,
                           rr_ray* gather_out = nullptr, uint32_t gather_n = 0);
 
+// The keys of rays[0, n) (as the keys kernel computes them for plan, with
+// the identity index) sorted by the single-segment sort with 8-bit digits
+// and kpt keys per thread, the histogram counted while the keys are
+// computed, and the rays gathered into key order by the last pass
+// (rays_out[i] = rays[idx[i]]).  keys / idx receive n entries; ws holds the
+// sort workspace of seg_layout(n, 1, key bits, 8, kpt).
+rr_status launch_keys_sort_gather(const rr_ray* rays, int64_t n, const KeyPlan& plan, void* keys, uint32_t* idx,
+                                  uint32_t kpt, void* ws, size_t ws_bytes, rr_ray* rays_out, hipStream_t st);
+
 // Runs the one-time occupancy queries of a sort configuration, so that a
 // later stream capture records kernel launches only.
 void sort_warm(uint32_t key_bits, uint32_t db, uint32_t kpt);
