@@ -184,6 +184,77 @@ def test_fused_adaptive_updates_the_table(rr):
             assert table.numpy().tobytes() == ref.cells.tobytes(), it
 
 
+def test_fused_dense_every_key_method(rr):
+    """Without compaction the fused call computes the keys and counts the
+    sort's digit histograms in one kernel: every key method and width gives
+    the oracle's permutation, and the hits scattered back equal the unsorted
+    trace bit for bit."""
+    w = W.city_small(seed=17, width=160, height=90, depth=1)
+    lo, hi = O.scene_box(w.tris)
+    n = w.rays.shape[0]
+    with rr.Scene(w.tris) as sc:
+        rays = to_dev(w.rays)
+        base = rr.rr_trace(sc, rays)
+        base_np = rr.hits_to_numpy(base)
+        assert 0 < np.mean(base_np["prim"] >= 0) < 1
+        cases = [(k, 32) for k in LAYOUTS] + [(rr.RR_KEY_TWO_POINT_ADAPTIVE, b) for b in (32, 64)] + \
+                [(rr.RR_KEY_TWO_POINT_REAL, b) for b in (32, 64)]
+        for kind, bits in cases:
+            aux = oaux = None
+            if kind == rr.RR_KEY_TWO_POINT_ADAPTIVE:
+                # a table with traced lengths in it, mirrored by the oracle's
+                aux = rr.LengthTable(rr.key_params(kind, bits, lo, hi, 0.25))
+                oaux = O.LengthTable(lo, hi, 0.25)
+                aux.accumulate(rays, base)
+                oaux.accumulate(w.rays, base_np)
+                torch.cuda.synchronize()
+                assert aux.numpy().tobytes() == oaux.cells.tobytes()
+            elif kind == rr.RR_KEY_TWO_POINT_REAL:
+                aux, oaux = base, base_np
+            p = rr.key_params(kind, bits, lo, hi, 0.25, aux=aux)
+            want = O.keys(w.rays, kind, bits, lo, hi, aux=oaux)
+            _, want_perm = O.sort_pairs(want)
+            hits, perm, cnt = rr.rr_reorder_and_trace(sc, rays, p, flags=rr.RR_HITS_ORIGINAL_ORDER)
+            assert int(cnt.cpu().numpy()[0]) == n
+            assert np.array_equal(perm.cpu().numpy().view(np.uint32), want_perm), (kind, bits)
+            assert rr.hits_to_numpy(hits).tobytes() == base_np.tobytes(), (kind, bits)
+
+
+def test_fused_dense_past_2_24_rays(rr):
+    """From 2^24 keys on the sort takes 16 keys per thread; the fused call's
+    keys-and-histogram kernel feeds that schedule too.  Permutation against
+    the oracle's keys and stable order; hits on a sample against the
+    oracle's trace, all hits scattered back against the unsorted trace."""
+    w = W.city_small(seed=23, width=64, height=36, depth=1, n=8, n_clutter=2000)
+    lo, hi = O.scene_box(w.tris)
+    n = (1 << 24) + 4097
+    rng = np.random.default_rng(24)
+    r = np.empty((n, 8), np.float32)
+    r[:, 0:3] = rng.uniform(lo, hi, (n, 3))
+    d = rng.normal(size=(n, 3))
+    r[:, 4:7] = d / np.linalg.norm(d, axis=1, keepdims=True)
+    r[:, 3] = 0.0
+    r[:, 7] = np.inf
+    for bits in (64, 32):
+        kind = O.KIND_OT if bits == 64 else O.KIND_OD
+        want = O.keys(r, kind, bits, lo, hi)
+        want_perm = np.lexsort((np.arange(n, dtype=np.uint32), want)).astype(np.uint32)
+        with rr.Scene(w.tris) as sc:
+            rays = to_dev(r)
+            p = rr.key_params(kind, bits, lo, hi)
+            hits, perm, _ = rr.rr_reorder_and_trace(sc, rays, p, flags=0)
+            got_perm = perm.cpu().numpy().view(np.uint32)
+            assert np.array_equal(got_perm, want_perm), bits
+            back = rr.rr_scatter_hits(hits, perm)
+            assert torch.equal(back.view(torch.int32), rr.rr_trace(sc, rays).view(torch.int32)), bits
+            h = rr.hits_to_numpy(hits)
+            sample = rng.choice(n, 4096, replace=False)
+            ref = O.BVH(w.tris).trace(r[want_perm[sample]])
+            assert h[sample].tobytes() == ref.tobytes(), bits
+            del rays, hits, perm, back
+            torch.cuda.empty_cache()
+
+
 def test_batch_mixes_key_methods(rr):
     w = W.city_small(seed=21, width=200, height=120, depth=1, n=16, n_clutter=20000)
     lo, hi = O.scene_box(w.tris)
