@@ -10,7 +10,8 @@
 //    passes per segment (a single sort spreads them over one copy per XCD,
 //    so that few atomics meet on one device word, and a block counts into
 //    eight LDS copies, so that lanes with equal digits seldom meet on one
-//    LDS word);
+//    LDS word); for the fused call's dense sort, k_keys_hist computes the
+//    keys from the rays and counts them in the same pass instead;
 //  * k_seg_pass blocks (512 threads) are persistent.  A sort that has the
 //    device to itself takes tiles in a fixed order (block b: tiles b,
 //    b + G, ...), so no shared tile counter is contended; the batched layer,
