@@ -62,8 +62,10 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
                     help="offered loads, fractions of the measured batched capacity")
-    ap.add_argument("--phases", default="all", choices=["all", "trace"],
-                    help="'trace' times only the sorted and unsorted traces (for counter runs)")
+    ap.add_argument("--phases", default="all", choices=["all", "trace", "trace4m"],
+                    help="'trace' times only the sorted and unsorted traces of the headline wavefront, "
+                         "'trace4m' the shuffled, key-sorted and generation orders of first-bounce rays "
+                         "in the 4M-triangle city (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
     a = ap.parse_args()
@@ -110,6 +112,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     rr.load()
+    if args.phases == "trace4m":
+        trace_orders_4m(torch, rr, W, dev, args)
+        return
 
     w = W.bounce2_1080p()
     n = w.rays.shape[0]
@@ -474,16 +479,52 @@ def shuffled_input(torch, rr, W, scene, rays, n, dev, stream, steps):
         return out
 
     res = {"city1M_bounce2_1080p": study(scene, rays, n)}
-    c = W.city(5, 200, 200, 3_520_000)
+    c, r = city4m_bounce1_2160p(W)
     with rr.Scene(c.tris) as sc4:
-        r = W.camera_rays(5, 3840, 2160, (100.0, 120.0, 100.0))
-        r, alive = W.bounce(c, 5, 300, r, np.ones(r.shape[0], np.uint8))
-        r = np.ascontiguousarray(r[alive.astype(bool)])
         rd = torch.from_numpy(r).to(dev)
         res["city4M_bounce1_2160p"] = study(sc4, rd, r.shape[0])
         del rd
     torch.cuda.empty_cache()
     return res
+
+
+def city4m_bounce1_2160p(W):
+    """The 4M-triangle city (the grid city scaled 2x2) and its first-bounce
+    rays at 3840x2160 that left a surface (the dead slots dropped)."""
+    c = W.city(5, 200, 200, 3_520_000)
+    r = W.camera_rays(5, 3840, 2160, (100.0, 120.0, 100.0))
+    r, alive = W.bounce(c, 5, 300, r, np.ones(r.shape[0], np.uint8))
+    return c, np.ascontiguousarray(r[alive.astype(bool)])
+
+
+def trace_orders_4m(torch, rr, W, dev, args):
+    """For counter runs: the first-bounce rays of the 4M-triangle city traced
+    in three orders, a seeded random permutation (shuffled), that order
+    sorted by origin-direction 32-bit keys (keys, sort and gather run once
+    before), and the generation order.  The trace launches come in that
+    order, warmup and steps alike, so dispatch i is order i mod 3."""
+    c, r = city4m_bounce1_2160p(W)
+    n = r.shape[0]
+    with rr.Scene(c.tris) as sc:
+        lo, hi = sc.bounds()
+        gen = torch.from_numpy(r).to(dev)
+        perm = torch.from_numpy(np.random.default_rng(7).permutation(n)).to(dev)
+        sh = gen.index_select(0, perm).contiguous()
+        p = rr.key_params(1, 32, lo, hi, 0.25)
+        k, idx, _ = rr.rr_compute_keys(sh, p)
+        rr.rr_sort(k, idx, key_bits=32)
+        srt = rr.rr_gather(sh, idx)
+        hits = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        for _ in range(args.warmup + args.steps):
+            for rays in (sh, srt, gen):
+                rr.rr_trace(sc, rays, hits=hits)
+        torch.cuda.synchronize()
+        if args.copy_calibration:
+            copy_calibration(torch, dev)
+        print(json.dumps({"phases": "trace4m", "rays": int(n), "triangles": int(c.tris.shape[0]),
+                          "orders": ["shuffled", "od32_sorted", "generation"], "steps": args.steps,
+                          "warmup": args.warmup, "sources_sha256": sources_digest()}))
 
 
 def shadow(torch, rr, W, scene, dev, stream, steps):
