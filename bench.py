@@ -62,10 +62,10 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
                     help="offered loads, fractions of the measured batched capacity")
-    ap.add_argument("--phases", default="all", choices=["all", "trace", "trace4m"],
+    ap.add_argument("--phases", default="all", choices=["all", "trace", "trace4m", "sort"],
                     help="'trace' times only the sorted and unsorted traces of the headline wavefront, "
                          "'trace4m' the shuffled, key-sorted and generation orders of first-bounce rays "
-                         "in the 4M-triangle city (for counter runs)")
+                         "in the 4M-triangle city, 'sort' only sorts (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
     a = ap.parse_args()
@@ -114,6 +114,9 @@ def main():
     rr.load()
     if args.phases == "trace4m":
         trace_orders_4m(torch, rr, W, dev, args)
+        return
+    if args.phases == "sort":
+        sorts_only(torch, rr, W, dev, args)
         return
 
     w = W.bounce2_1080p()
@@ -525,6 +528,40 @@ def trace_orders_4m(torch, rr, W, dev, args):
         print(json.dumps({"phases": "trace4m", "rays": int(n), "triangles": int(c.tris.shape[0]),
                           "orders": ["shuffled", "od32_sorted", "generation"], "steps": args.steps,
                           "warmup": args.warmup, "sources_sha256": sources_digest()}))
+
+
+def sorts_only(torch, rr, W, dev, args):
+    """For counter runs: device-wide sorts of 64-bit pairs, warmup and steps
+    alike, in this order: the headline's Two Point keys (2,073,600), random
+    keys (2,073,600), random keys (8,294,400).  Each sort is one setup, one
+    histogram and 8 scatter launches."""
+    w = W.bounce2_1080p()
+    with rr.Scene(w.tris) as sc:
+        lo, hi = sc.bounds()
+    rays = torch.from_numpy(w.rays).to(dev)
+    k_real, _, _ = rr.rr_compute_keys(rays, rr.key_params(2, 64, lo, hi, 0.25))
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    cases = [("ot64_headline", k_real),
+             ("random_2M", torch.randint(-(1 << 62), 1 << 62, (k_real.shape[0],), dtype=torch.int64, device=dev,
+                                         generator=g)),
+             ("random_8M", torch.randint(-(1 << 62), 1 << 62, (8294400,), dtype=torch.int64, device=dev,
+                                         generator=g))]
+    work = []
+    for name, k0 in cases:
+        m = k0.shape[0]
+        work.append((k0, k0.clone(), torch.empty(m, dtype=torch.int32, device=dev),
+                     rr.workspace(rr.sort_workspace_size(m, 64), dev)))
+    torch.cuda.synchronize()
+    for _ in range(args.warmup + args.steps):
+        for k0, k, idx, ws in work:
+            k.copy_(k0)
+            torch.arange(k0.shape[0], dtype=torch.int32, device=dev, out=idx)
+            rr.rr_sort(k, idx, ws=ws)
+    torch.cuda.synchronize()
+    if args.copy_calibration:
+        copy_calibration(torch, dev)
+    print(json.dumps({"phases": "sort", "cases": [c[0] for c in cases], "steps": args.steps, "warmup": args.warmup}))
 
 
 def shadow(torch, rr, W, scene, dev, stream, steps):
