@@ -35,12 +35,21 @@ typedef struct rr_segment {
 } rr_segment;
 
 /* Launch shape of a batch: radix digit width (4 or 8 bits), keys per
- * thread of a sort tile (8 or 16), and the trace's lane-refill threshold
- * (1..64).  Results do not depend on it. */
+ * thread of a sort tile (8 or 16), the trace's lane-refill threshold
+ * (1..64), and the order in which the sort's scatter passes take tiles:
+ * RR_TILES_COUNTER (0, the default) hands them out from a counter, so a
+ * tile is only awaited while a running block holds it, which keeps the
+ * decoupled look-back from its slow fallback when other kernels share the
+ * device (the server's concurrent batches); RR_TILES_FIXED (1) gives block
+ * b the tiles b, b + G, ... with no counter atomics, faster for a batch
+ * that has the device to itself.  Results do not depend on the shape. */
+#define RR_TILES_COUNTER 0u
+#define RR_TILES_FIXED 1u
 typedef struct rr_batch_config {
   uint32_t digit_bits;
   uint32_t keys_per_thread;
   uint32_t refill;
+  uint32_t tile_order;
 } rr_batch_config;
 
 typedef struct rr_batch_s* rr_batch;
@@ -66,7 +75,9 @@ rr_status rr_batch_set_config(rr_batch b, const rr_batch_config* cfg);
 rr_status rr_batch_run(rr_batch b, const rr_segment* segs, int32_t nseg, uint32_t flags, void* stream);
 
 /* Times every launch shape on this batch of segments (reps runs each,
- * median) and keeps the fastest; returns it and its time.  Synchronises. */
+ * median) and keeps the fastest; returns it and its time.  Synchronises.
+ * It runs the batch alone, so it may choose RR_TILES_FIXED: a batch that
+ * will share the device should keep RR_TILES_COUNTER. */
 rr_status rr_batch_autotune(rr_batch b, const rr_segment* segs, int32_t nseg, int32_t reps, rr_batch_config* best,
                             float* best_ms, void* stream);
 rr_status rr_batch_destroy(rr_batch b);

@@ -19,5 +19,6 @@ from .rr import (  # noqa: F401
     workspace,
 )
 from .batch import (  # noqa: F401
-    EXTRA_EXPORTS, RR_BATCH_EAGER, Batch, Server, load_tuned, save_tuned, segment, tuning_db_path,
+    EXTRA_EXPORTS, RR_BATCH_EAGER, RR_TILES_COUNTER, RR_TILES_FIXED, Batch, Server, load_tuned, save_tuned, segment,
+    tuning_db_path,
 )

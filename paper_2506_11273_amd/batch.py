@@ -31,11 +31,22 @@ class Segment(ctypes.Structure):
                 ("n", ctypes.c_int64), ("key", KeyParams)]
 
 
+RR_TILES_COUNTER = 0
+RR_TILES_FIXED = 1
+
+
 class BatchConfig(ctypes.Structure):
-    _fields_ = [("digit_bits", ctypes.c_uint32), ("keys_per_thread", ctypes.c_uint32), ("refill", ctypes.c_uint32)]
+    _fields_ = [("digit_bits", ctypes.c_uint32), ("keys_per_thread", ctypes.c_uint32), ("refill", ctypes.c_uint32),
+                ("tile_order", ctypes.c_uint32)]
+
+    @classmethod
+    def of(cls, config: dict):
+        return cls(config["digit_bits"], config["keys_per_thread"], config["refill"],
+                   config.get("tile_order", RR_TILES_COUNTER))
 
     def as_dict(self):
-        return {"digit_bits": self.digit_bits, "keys_per_thread": self.keys_per_thread, "refill": self.refill}
+        return {"digit_bits": self.digit_bits, "keys_per_thread": self.keys_per_thread, "refill": self.refill,
+                "tile_order": self.tile_order}
 
 
 class ServerConfig(ctypes.Structure):
@@ -108,7 +119,7 @@ class Batch:
         h = ctypes.c_void_p()
         cfg = None
         if config is not None:
-            cfg = BatchConfig(config["digit_bits"], config["keys_per_thread"], config["refill"])
+            cfg = BatchConfig.of(config)
         _check(L.rr_batch_create(scene.handle, max_rays, max_segments, ctypes.byref(cfg) if cfg else None,
                                  ctypes.byref(h)), "rr_batch_create")
         self.handle = h
@@ -121,7 +132,7 @@ class Batch:
         return {"device_bytes": b.value, "config": c.as_dict()}
 
     def set_config(self, config: dict):
-        c = BatchConfig(config["digit_bits"], config["keys_per_thread"], config["refill"])
+        c = BatchConfig.of(config)
         _check(load().rr_batch_set_config(self.handle, ctypes.byref(c)), "rr_batch_set_config")
 
     def run(self, segs: Sequence[Segment], flags: int = _rr.RR_HITS_ORIGINAL_ORDER, stream=None):

@@ -148,7 +148,7 @@ struct rr_batch_s {
   int device = 0;
   int64_t cap = 0;
   int32_t max_seg = 0;
-  rr_batch_config cfg{8, 16, kDefaultRefill};
+  rr_batch_config cfg{8, 16, kDefaultRefill, RR_TILES_COUNTER};
   char* dev = nullptr;  // one device allocation for everything below
   size_t bytes = 0;
   size_t off_hdr = 0, off_segs = 0, off_shdr = 0, off_ssegs = 0, off_keys = 0, off_idx = 0, off_rays = 0,
@@ -159,7 +159,7 @@ struct rr_batch_s {
   int ring = 0;
   hipStream_t capture = nullptr;
   struct Graph {
-    uint32_t kb, db, kpt, refill;
+    uint32_t kb, db, kpt, refill, order;
     hipGraphExec_t exec;
   };
   std::vector<Graph> graphs;
@@ -178,7 +178,7 @@ size_t batch_sort_ws(int64_t cap, int32_t max_seg) {
 
 bool valid_cfg(const rr_batch_config& c) {
   return (c.digit_bits == 4 || c.digit_bits == 8) && (c.keys_per_thread == 8 || c.keys_per_thread == 16) &&
-         c.refill >= 1 && c.refill <= 64;
+         c.refill >= 1 && c.refill <= 64 && (c.tile_order == RR_TILES_COUNTER || c.tile_order == RR_TILES_FIXED);
 }
 
 // Enqueues the whole batched path on st (eagerly or into a capture).
@@ -201,7 +201,7 @@ rr_status enqueue(rr_batch b, uint32_t kb, const rr_batch_config& c, hipStream_t
   RR_LAUNCH_CHECK();
   const SegLayout L = seg_layout(b->cap, (uint32_t)b->max_seg, kb, c.digit_bits, c.keys_per_thread);
   rr_status r = launch_seg_sort(d + b->off_keys, idx, L, d + b->off_ws, shdr, ssegs, nullptr, (uint32_t)b->cap, kb,
-                                c.digit_bits, c.keys_per_thread, true, st);
+                                c.digit_bits, c.keys_per_thread, c.tile_order == RR_TILES_COUNTER, st);
   if (r != RR_OK) return r;
   hipLaunchKernelGGL(k_batch_gather, dim3(grid), dim3(kBatchBlock), 0, st, hdr, segs, idx, srays);
   RR_LAUNCH_CHECK();
@@ -216,7 +216,8 @@ rr_status enqueue(rr_batch b, uint32_t kb, const rr_batch_config& c, hipStream_t
 
 rr_status graph_for(rr_batch b, uint32_t kb, const rr_batch_config& c, hipGraphExec_t* out) {
   for (auto& g : b->graphs)
-    if (g.kb == kb && g.db == c.digit_bits && g.kpt == c.keys_per_thread && g.refill == c.refill) {
+    if (g.kb == kb && g.db == c.digit_bits && g.kpt == c.keys_per_thread && g.refill == c.refill &&
+        g.order == c.tile_order) {
       *out = g.exec;
       return RR_OK;
     }
@@ -237,7 +238,7 @@ rr_status graph_for(rr_batch b, uint32_t kb, const rr_batch_config& c, hipGraphE
   const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (ei != hipSuccess) return RR_ERR_DEVICE;
-  b->graphs.push_back({kb, c.digit_bits, c.keys_per_thread, c.refill, exec});
+  b->graphs.push_back({kb, c.digit_bits, c.keys_per_thread, c.refill, c.tile_order, exec});
   *out = exec;
   return RR_OK;
 }
@@ -427,35 +428,33 @@ rr_status rr_batch_autotune(rr_batch b, const rr_segment* segs, int32_t nseg, in
   rr_batch_config win = keep;
   float win_ms = 1e30f;
   rr_status r = RR_OK;
-  for (uint32_t db : {8u, 4u}) {
-    for (uint32_t kpt : {16u, 8u}) {
-      for (uint32_t refill : {8u, 16u, 32u, 48u}) {
-        const rr_batch_config c{db, kpt, refill};
-        if ((r = rr_batch_set_config(b, &c)) != RR_OK) break;
-        if ((r = rr_batch_run(b, segs, nseg, 0, stream)) != RR_OK) break;  // capture + warm-up
-        std::vector<float> t;
-        for (int32_t i = 0; i < reps && r == RR_OK; ++i) {
-          (void)hipEventRecord(e0, st);
-          if ((r = rr_batch_run(b, segs, nseg, 0, stream)) != RR_OK) break;
-          (void)hipEventRecord(e1, st);
-          if (hipEventSynchronize(e1) != hipSuccess) {
-            r = RR_ERR_DEVICE;
-            break;
-          }
-          float ms = 0;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          t.push_back(ms);
-        }
-        if (r != RR_OK) break;
-        std::sort(t.begin(), t.end());
-        if (t[t.size() / 2] < win_ms) {
-          win_ms = t[t.size() / 2];
-          win = c;
-        }
+  std::vector<rr_batch_config> shapes;
+  for (uint32_t db : {8u, 4u})
+    for (uint32_t kpt : {16u, 8u})
+      for (uint32_t refill : {8u, 16u, 32u, 48u})
+        for (uint32_t order : {RR_TILES_COUNTER, RR_TILES_FIXED}) shapes.push_back({db, kpt, refill, order});
+  for (const rr_batch_config& c : shapes) {
+    if ((r = rr_batch_set_config(b, &c)) != RR_OK) break;
+    if ((r = rr_batch_run(b, segs, nseg, 0, stream)) != RR_OK) break;  // capture + warm-up
+    std::vector<float> t;
+    for (int32_t i = 0; i < reps && r == RR_OK; ++i) {
+      (void)hipEventRecord(e0, st);
+      if ((r = rr_batch_run(b, segs, nseg, 0, stream)) != RR_OK) break;
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        r = RR_ERR_DEVICE;
+        break;
       }
-      if (r != RR_OK) break;
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      t.push_back(ms);
     }
     if (r != RR_OK) break;
+    std::sort(t.begin(), t.end());
+    if (t[t.size() / 2] < win_ms) {
+      win_ms = t[t.size() / 2];
+      win = c;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
