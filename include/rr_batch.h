@@ -36,7 +36,9 @@ typedef struct rr_segment {
 
 /* Launch shape of a batch: radix digit width (4 or 8 bits), keys per
  * thread of a sort tile (8 or 16), the trace's lane-refill threshold
- * (1..64), and the order in which the sort's scatter passes take tiles:
+ * (1..64), the trace kernel's block size (128, 256 or 512 threads; the
+ * closest-hit trace on quantised nodes, the other scenes trace with 256),
+ * and the order in which the sort's scatter passes take tiles:
  * RR_TILES_COUNTER (0, the default) hands them out from a counter, so a
  * tile is only awaited while a running block holds it, which keeps the
  * decoupled look-back from its slow fallback when other kernels share the
@@ -50,6 +52,7 @@ typedef struct rr_batch_config {
   uint32_t keys_per_thread;
   uint32_t refill;
   uint32_t tile_order;
+  uint32_t trace_block;
 } rr_batch_config;
 
 typedef struct rr_batch_s* rr_batch;

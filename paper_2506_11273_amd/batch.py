@@ -37,16 +37,16 @@ RR_TILES_FIXED = 1
 
 class BatchConfig(ctypes.Structure):
     _fields_ = [("digit_bits", ctypes.c_uint32), ("keys_per_thread", ctypes.c_uint32), ("refill", ctypes.c_uint32),
-                ("tile_order", ctypes.c_uint32)]
+                ("tile_order", ctypes.c_uint32), ("trace_block", ctypes.c_uint32)]
 
     @classmethod
     def of(cls, config: dict):
         return cls(config["digit_bits"], config["keys_per_thread"], config["refill"],
-                   config.get("tile_order", RR_TILES_COUNTER))
+                   config.get("tile_order", RR_TILES_COUNTER), config.get("trace_block", 256))
 
     def as_dict(self):
         return {"digit_bits": self.digit_bits, "keys_per_thread": self.keys_per_thread, "refill": self.refill,
-                "tile_order": self.tile_order}
+                "tile_order": self.tile_order, "trace_block": self.trace_block}
 
 
 class ServerConfig(ctypes.Structure):

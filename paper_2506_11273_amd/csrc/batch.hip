@@ -148,7 +148,7 @@ struct rr_batch_s {
   int device = 0;
   int64_t cap = 0;
   int32_t max_seg = 0;
-  rr_batch_config cfg{8, 16, kDefaultRefill, RR_TILES_COUNTER};
+  rr_batch_config cfg{8, 16, kDefaultRefill, RR_TILES_COUNTER, 256};
   char* dev = nullptr;  // one device allocation for everything below
   size_t bytes = 0;
   size_t off_hdr = 0, off_segs = 0, off_shdr = 0, off_ssegs = 0, off_keys = 0, off_idx = 0, off_rays = 0,
@@ -159,7 +159,7 @@ struct rr_batch_s {
   int ring = 0;
   hipStream_t capture = nullptr;
   struct Graph {
-    uint32_t kb, db, kpt, refill, order;
+    uint32_t kb, db, kpt, refill, order, block;
     hipGraphExec_t exec;
   };
   std::vector<Graph> graphs;
@@ -178,7 +178,8 @@ size_t batch_sort_ws(int64_t cap, int32_t max_seg) {
 
 bool valid_cfg(const rr_batch_config& c) {
   return (c.digit_bits == 4 || c.digit_bits == 8) && (c.keys_per_thread == 8 || c.keys_per_thread == 16) &&
-         c.refill >= 1 && c.refill <= 64 && (c.tile_order == RR_TILES_COUNTER || c.tile_order == RR_TILES_FIXED);
+         c.refill >= 1 && c.refill <= 64 && (c.tile_order == RR_TILES_COUNTER || c.tile_order == RR_TILES_FIXED) &&
+         (c.trace_block == 128 || c.trace_block == 256 || c.trace_block == 512);
 }
 
 // Enqueues the whole batched path on st (eagerly or into a capture).
@@ -207,7 +208,7 @@ rr_status enqueue(rr_batch b, uint32_t kb, const rr_batch_config& c, hipStream_t
   RR_LAUNCH_CHECK();
   const uint32_t* total = reinterpret_cast<const uint32_t*>(d + b->off_hdr + offsetof(BatchHdr, total));
   r = launch_trace_refill(b->scene->d, reinterpret_cast<const rr_ray*>(srays), nullptr, b->cap, total,
-                          reinterpret_cast<rr_hit*>(shits), c.refill, st);
+                          reinterpret_cast<rr_hit*>(shits), c.refill, st, c.trace_block);
   if (r != RR_OK) return r;
   hipLaunchKernelGGL(k_batch_out, dim3(grid), dim3(kBatchBlock), 0, st, hdr, segs, idx, shits);
   RR_LAUNCH_CHECK();
@@ -217,7 +218,7 @@ rr_status enqueue(rr_batch b, uint32_t kb, const rr_batch_config& c, hipStream_t
 rr_status graph_for(rr_batch b, uint32_t kb, const rr_batch_config& c, hipGraphExec_t* out) {
   for (auto& g : b->graphs)
     if (g.kb == kb && g.db == c.digit_bits && g.kpt == c.keys_per_thread && g.refill == c.refill &&
-        g.order == c.tile_order) {
+        g.order == c.tile_order && g.block == c.trace_block) {
       *out = g.exec;
       return RR_OK;
     }
@@ -238,7 +239,7 @@ rr_status graph_for(rr_batch b, uint32_t kb, const rr_batch_config& c, hipGraphE
   const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (ei != hipSuccess) return RR_ERR_DEVICE;
-  b->graphs.push_back({kb, c.digit_bits, c.keys_per_thread, c.refill, c.tile_order, exec});
+  b->graphs.push_back({kb, c.digit_bits, c.keys_per_thread, c.refill, c.tile_order, c.trace_block, exec});
   *out = exec;
   return RR_OK;
 }
@@ -432,7 +433,8 @@ rr_status rr_batch_autotune(rr_batch b, const rr_segment* segs, int32_t nseg, in
   for (uint32_t db : {8u, 4u})
     for (uint32_t kpt : {16u, 8u})
       for (uint32_t refill : {8u, 16u, 32u, 48u})
-        for (uint32_t order : {RR_TILES_COUNTER, RR_TILES_FIXED}) shapes.push_back({db, kpt, refill, order});
+        for (uint32_t order : {RR_TILES_COUNTER, RR_TILES_FIXED})
+          for (uint32_t block : {256u, 128u, 512u}) shapes.push_back({db, kpt, refill, order, block});
   for (const rr_batch_config& c : shapes) {
     if ((r = rr_batch_set_config(b, &c)) != RR_OK) break;
     if ((r = rr_batch_run(b, segs, nseg, 0, stream)) != RR_OK) break;  // capture + warm-up

@@ -130,8 +130,10 @@ struct DeviceScene {
 rr_status launch_trace_stats(const DeviceScene& s, const rr_ray* rays, int64_t n_max, rr_hit* hits,
                              uint64_t* stats_dev, hipStream_t st);
 void trace_warm();
+// block: threads per workgroup of the trace kernel, 128, 256 or 512.
 rr_status launch_trace_refill(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
-                              const uint32_t* count_dev, rr_hit* hits, uint32_t refill, hipStream_t st);
+                              const uint32_t* count_dev, rr_hit* hits, uint32_t refill, hipStream_t st,
+                              uint32_t block = 256);
 // Any-hit (occlusion) trace: some triangle hit in (tmin, tmax), or a miss.
 rr_status launch_trace_any(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
                            const uint32_t* count_dev, rr_hit* hits, hipStream_t st);

@@ -389,7 +389,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
 
 constexpr int kTraceBlock = 256;
 
-template <bool STATS, bool QNODE, bool ANY>
+template <int BLOCK, bool STATS, bool QNODE, bool ANY>
 uint32_t resident_blocks() {
   static uint32_t cached = 0;
   if (cached) return cached;
@@ -397,23 +397,23 @@ uint32_t resident_blocks() {
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
     cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace4<kTraceBlock, STATS, QNODE, ANY>, kTraceBlock, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace4<BLOCK, STATS, QNODE, ANY>, BLOCK, 0) !=
           hipSuccess ||
       per <= 0)
-    per = 4;
+    per = 1024 / BLOCK;
   cached = (uint32_t)(cus * per);
   return cached;
 }
 
-template <bool STATS, bool QNODE, bool ANY>
+template <int BLOCK, bool STATS, bool QNODE, bool ANY>
 rr_status launch4q(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
                    const uint32_t* count_dev, rr_hit* hits, uint32_t refill, TraceStats* stats, hipStream_t st) {
   // enough waves to fill the device, but at least one full wave of rays each
   const uint64_t waves_needed = (uint64_t)(n_max + kWave - 1) / kWave;
-  const uint64_t blocks_needed = (waves_needed + kTraceBlock / kWave - 1) / (kTraceBlock / kWave);
-  const uint32_t blocks = (uint32_t)std::min<uint64_t>(blocks_needed, resident_blocks<STATS, QNODE, ANY>());
-  hipLaunchKernelGGL((k_trace4<kTraceBlock, STATS, QNODE, ANY>), dim3(blocks), dim3(kTraceBlock), 0, st, s.nodes,
-                     s.tris, s.root, reinterpret_cast<const float4*>(rays), idx, count_dev, (uint32_t)n_max,
+  const uint64_t blocks_needed = (waves_needed + BLOCK / kWave - 1) / (BLOCK / kWave);
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>(blocks_needed, resident_blocks<BLOCK, STATS, QNODE, ANY>());
+  hipLaunchKernelGGL((k_trace4<BLOCK, STATS, QNODE, ANY>), dim3(blocks), dim3(BLOCK), 0, st, s.nodes, s.tris, s.root,
+                     reinterpret_cast<const float4*>(rays), idx, count_dev, (uint32_t)n_max,
                      reinterpret_cast<float4*>(hits), refill, stats);
   RR_LAUNCH_CHECK();
   return RR_OK;
@@ -421,12 +421,19 @@ rr_status launch4q(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx
 
 template <bool STATS, bool ANY = false>
 rr_status launch4(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
-                  const uint32_t* count_dev, rr_hit* hits, uint32_t refill, TraceStats* stats, hipStream_t st) {
+                  const uint32_t* count_dev, rr_hit* hits, uint32_t refill, TraceStats* stats, hipStream_t st,
+                  uint32_t block = kTraceBlock) {
   if (n_max <= 0) return RR_OK;
   if (refill < 1) refill = 1;
   if (refill > (uint32_t)kWave) refill = kWave;
-  return s.quantised ? launch4q<STATS, true, ANY>(s, rays, idx, n_max, count_dev, hits, refill, stats, st)
-                     : launch4q<STATS, false, ANY>(s, rays, idx, n_max, count_dev, hits, refill, stats, st);
+  // the other block sizes exist for the closest-hit trace on quantised nodes
+  if (!STATS && !ANY && s.quantised && block == 128)
+    return launch4q<128, false, true, false>(s, rays, idx, n_max, count_dev, hits, refill, stats, st);
+  if (!STATS && !ANY && s.quantised && block == 512)
+    return launch4q<512, false, true, false>(s, rays, idx, n_max, count_dev, hits, refill, stats, st);
+  return s.quantised ? launch4q<kTraceBlock, STATS, true, ANY>(s, rays, idx, n_max, count_dev, hits, refill, stats, st)
+                     : launch4q<kTraceBlock, STATS, false, ANY>(s, rays, idx, n_max, count_dev, hits, refill, stats,
+                                                                st);
 }
 
 }  // namespace
@@ -437,8 +444,9 @@ rr_status launch_trace(const DeviceScene& s, const rr_ray* rays, const uint32_t*
 }
 
 rr_status launch_trace_refill(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
-                              const uint32_t* count_dev, rr_hit* hits, uint32_t refill, hipStream_t st) {
-  return launch4<false>(s, rays, idx, n_max, count_dev, hits, refill, nullptr, st);
+                              const uint32_t* count_dev, rr_hit* hits, uint32_t refill, hipStream_t st,
+                              uint32_t block) {
+  return launch4<false>(s, rays, idx, n_max, count_dev, hits, refill, nullptr, st, block);
 }
 
 rr_status launch_trace_any(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
@@ -447,12 +455,14 @@ rr_status launch_trace_any(const DeviceScene& s, const rr_ray* rays, const uint3
 }
 
 void trace_warm() {
-  (void)resident_blocks<false, false, false>();
-  (void)resident_blocks<false, true, false>();
-  (void)resident_blocks<true, false, false>();
-  (void)resident_blocks<true, true, false>();
-  (void)resident_blocks<false, false, true>();
-  (void)resident_blocks<false, true, true>();
+  (void)resident_blocks<kTraceBlock, false, false, false>();
+  (void)resident_blocks<kTraceBlock, false, true, false>();
+  (void)resident_blocks<kTraceBlock, true, false, false>();
+  (void)resident_blocks<kTraceBlock, true, true, false>();
+  (void)resident_blocks<kTraceBlock, false, false, true>();
+  (void)resident_blocks<kTraceBlock, false, true, true>();
+  (void)resident_blocks<128, false, true, false>();
+  (void)resident_blocks<512, false, true, false>();
 }
 
 rr_status launch_trace_stats(const DeviceScene& s, const rr_ray* rays, int64_t n_max, rr_hit* hits,

@@ -158,18 +158,22 @@ def test_every_launch_shape_gives_identical_results(rr, city):
             for kpt in (16, 8):
                 for refill in (1, 16, 64):
                     for order in (rr.RR_TILES_COUNTER, rr.RR_TILES_FIXED):
-                        b.set_config({"digit_bits": db, "keys_per_thread": kpt, "refill": refill,
-                                      "tile_order": order})
-                        assert b.info()["config"]["tile_order"] == order
-                        b.run(seg_structs(rr, segs))
-                        torch.cuda.synchronize()
-                        outs.append([(s["hits"].cpu().numpy().tobytes(), s["perm"].cpu().numpy().tobytes())
-                                     for s in segs])
+                        for block in (128, 256, 512):
+                            b.set_config({"digit_bits": db, "keys_per_thread": kpt, "refill": refill,
+                                          "tile_order": order, "trace_block": block})
+                            cfg = b.info()["config"]
+                            assert cfg["tile_order"] == order and cfg["trace_block"] == block
+                            b.run(seg_structs(rr, segs))
+                            torch.cuda.synchronize()
+                            outs.append([(s["hits"].cpu().numpy().tobytes(), s["perm"].cpu().numpy().tobytes())
+                                         for s in segs])
         assert all(o == outs[0] for o in outs)
-        with pytest.raises(rr.RRError):
-            b.set_config({"digit_bits": 8, "keys_per_thread": 16, "refill": 8, "tile_order": 2})
+        for bad in ({"tile_order": 2}, {"trace_block": 64}, {"trace_block": 1024}):
+            with pytest.raises(rr.RRError):
+                b.set_config(dict({"digit_bits": 8, "keys_per_thread": 16, "refill": 8}, **bad))
         best, ms = b.autotune(seg_structs(rr, segs), reps=2)
         assert best["digit_bits"] in (4, 8) and best["tile_order"] in (0, 1) and ms > 0
+        assert best["trace_block"] in (128, 256, 512)
         b.run(seg_structs(rr, segs))
         check(rr, scene, segs, "tuned")
 
