@@ -315,6 +315,27 @@ def test_reorder_and_trace_with_compaction(rr):
             assert np.all(h["prim"][~live] == -1) and np.all(np.isinf(h["t"][~live]))
 
 
+def test_reorder_and_trace_dense_ragged_sizes(rr, soup65k):
+    """The dense fused call (keys and digit histograms in one kernel, 4096
+    rays per histogram unit) at ragged sizes around the unit and the sort
+    tile, one ray included: permutation against the oracle's stable order of
+    its keys, key-order hits against the plain trace through it."""
+    w = soup65k
+    lo, hi = O.scene_box(w.tris)
+    with rr.Scene(w.tris) as sc:
+        for n in (1, 2, 63, 4095, 4096, 4097, 8193, 12289):
+            rays_np = np.ascontiguousarray(w.rays[:n])
+            rays = to_dev(rays_np)
+            base = rr.hits_to_numpy(rr.rr_trace(sc, rays))
+            for kind, bits in [(O.KIND_OD, 32), (O.KIND_OT, 64)]:
+                _, want = O.sort_pairs(O.keys(rays_np, kind, bits, lo, hi))
+                p = rr.key_params(kind, bits, lo, hi)
+                hits, perm, cnt = rr.rr_reorder_and_trace(sc, rays, p, flags=0)
+                assert int(cnt.cpu().numpy()[0]) == n
+                assert np.array_equal(idx_np(perm), want), (n, kind, bits)
+                assert rr.hits_to_numpy(hits).tobytes() == base[want].tobytes(), (n, kind, bits)
+
+
 def test_reorder_and_trace_compaction_edges_every_flag(rr, soup65k):
     """Live sets at the edges (none, only the first slot, only the last slot,
     every other slot, all) through the fused call with the gather in the
