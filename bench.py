@@ -62,10 +62,11 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
                     help="offered loads, fractions of the measured batched capacity")
-    ap.add_argument("--phases", default="all", choices=["all", "trace", "trace4m", "sort"],
+    ap.add_argument("--phases", default="all", choices=["all", "trace", "trace4m", "sort", "batch"],
                     help="'trace' times only the sorted and unsorted traces of the headline wavefront, "
                          "'trace4m' the shuffled, key-sorted and generation orders of first-bounce rays "
-                         "in the 4M-triangle city, 'sort' only sorts (for counter runs)")
+                         "in the 4M-triangle city, 'sort' only sorts, 'batch' only runs the 64-wavefront "
+                         "batch graph in a fixed launch shape (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
     a = ap.parse_args()
@@ -122,6 +123,9 @@ def main():
     w = W.bounce2_1080p()
     n = w.rays.shape[0]
     scene = rr.Scene(w.tris, builder=args.builder)
+    if args.phases == "batch":
+        batch_only(torch, rr, W, scene, w, dev, args)
+        return
     lo, hi = scene.bounds()
     kind, bits = KEYS[args.key]
     params = rr.key_params(kind, bits, lo, hi, 0.25)
@@ -530,6 +534,24 @@ def trace_orders_4m(torch, rr, W, dev, args):
                           "warmup": args.warmup, "sources_sha256": sources_digest()}))
 
 
+# the batch's launch shape for profiler runs: the autotuner's choice on the
+# 64-wavefront batch (8-bit digits, 8 keys per thread, refill 8, fixed tile
+# order, 256-thread trace blocks)
+BATCH_PROFILE_SHAPE = {"digit_bits": 8, "keys_per_thread": 8, "refill": 8, "tile_order": 1, "trace_block": 256}
+
+
+def batch_only(torch, rr, W, scene, w, dev, args):
+    """For profiler runs: the 64-wavefront batch graph in BATCH_PROFILE_SHAPE,
+    warmup + steps launches."""
+    segs, keep, total = batch_segments(torch, rr, W, scene, w, dev)
+    with rr.Batch(scene, max_rays=total, max_segments=len(segs), config=BATCH_PROFILE_SHAPE) as b:
+        for _ in range(args.warmup + args.steps):
+            b.run(segs, flags=0)
+        torch.cuda.synchronize()
+    print(json.dumps({"phases": "batch", "segments": len(segs), "rays": total, "shape": BATCH_PROFILE_SHAPE,
+                      "steps": args.steps, "warmup": args.warmup}))
+
+
 def sorts_only(torch, rr, W, dev, args):
     """For counter runs: device-wide sorts of 64-bit pairs, warmup and steps
     alike, in this order: the headline's Two Point keys (2,073,600), random
@@ -670,10 +692,11 @@ def sort_sizes(torch, rr, dev, stream, reps=7):
     return out
 
 
-def batched(torch, rr, W, scene, w, dev, stream):
-    """64 wavefronts, sizes log-uniform in [4K, 2M], each drawn from the
-    primary or bounce 1-4 rays of the 1920x1080 city view, Two Point 64-bit
-    keys, reordered and traced in one graph launch."""
+def batch_segments(torch, rr, W, scene, w, dev):
+    """The 64 wavefronts of the batched section: sizes log-uniform in
+    [4K, 2M], each drawn from the primary or bounce 1-4 rays of the 1920x1080
+    city view, Two Point 64-bit keys.  Returns (segments, tensors kept alive,
+    total rays)."""
     c = w.city
     pools = []
     r = W.camera_rays(4, 1920, 1080, (c.nx / 2.0, 0.6 * max(c.nx, c.nz), c.nz / 2.0))
@@ -694,7 +717,13 @@ def batched(torch, rr, W, scene, w, dev, stream):
         hits = torch.empty((int(m), 4), dtype=torch.float32, device=dev)
         keep.append((rays, hits))
         segs.append(rr.segment(rays, hits, key))
-    total = int(sizes.sum())
+    return segs, keep, int(sizes.sum())
+
+
+def batched(torch, rr, W, scene, w, dev, stream):
+    """The 64 wavefronts reordered and traced in one graph launch (shape
+    from the autotuner), against the same wavefronts one call each."""
+    segs, keep, total = batch_segments(torch, rr, W, scene, w, dev)
     out = {"segments": len(segs), "rays": total}
     with rr.Batch(scene, max_rays=total, max_segments=len(segs)) as b:
         t0 = time.perf_counter()
