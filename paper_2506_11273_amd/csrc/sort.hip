@@ -15,10 +15,10 @@
 //  * k_seg_pass blocks (512 threads) are persistent.  A sort that has the
 //    device to itself takes tiles in a fixed order (block b: tiles b,
 //    b + G, ...), so no shared tile counter is contended; the batched layer,
-//    whose sorts may share the device with other kernels, takes them in order
-//    from an atomic counter, so that a tile is only ever held by a running
-//    block (each block takes its next ticket while it works on the current
-//    tile).  A tile is ranked by digit with wave64 ballots (a match over the
+//    whose sorts may share the device with other kernels, by default takes
+//    them in order from an atomic counter, so that a tile is only ever held
+//    by a running block (each block takes its next ticket while it works on
+//    the current tile).  A tile is ranked by digit with wave64 ballots (a match over the
 //    digit's bits gives each lane its peers; the lowest peer adds the group's
 //    size to the wave's digit count with one LDS atomic), its digit counts
 //    are published, the previous tiles of the same segment are looked back
