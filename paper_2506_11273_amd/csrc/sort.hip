@@ -136,6 +136,37 @@ __global__ void k_seg_init(const SortHdr* hdr, uint32_t* __restrict__ hist, uint
 // counts into one of kHistLaneCopies copies (lane mod 8), laid out so that
 // the copies of a word sit in different banks, and the copies are summed at
 // the flush.
+// Adds the block's lane-copy counts of the first `words` histogram words to
+// dst (device atomics, zero counts skipped) and clears them for reuse.  The
+// caller synchronises the block before and, to reuse s_h, after.
+__device__ __forceinline__ void flush_lane_hist(uint32_t* s_h, uint32_t stride, uint32_t words,
+                                                uint32_t* __restrict__ dst) {
+  for (uint32_t i = threadIdx.x; i < words; i += kSortThreads) {
+    uint32_t v = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < kHistLaneCopies; ++c) {
+      v += s_h[c * stride + i];
+      s_h[c * stride + i] = 0;
+    }
+    if (v) atomicAdd(&dst[i], v);
+  }
+}
+
+// Clears the look-back words of `tiles` tiles and `groups` groups of every
+// pass, spread over the grid.
+__device__ __forceinline__ void clear_lookback(uint32_t* __restrict__ status, uint32_t status_pass_stride,
+                                               uint32_t tiles, uint32_t* __restrict__ gstatus,
+                                               uint32_t gstatus_pass_stride, uint32_t groups, uint32_t passes,
+                                               uint32_t R) {
+  const uint32_t stride = gridDim.x * kSortThreads;
+  for (uint32_t p = 0; p < passes; ++p) {
+    for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < tiles * R; i += stride)
+      status[(size_t)p * status_pass_stride + i] = 0;
+    for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < groups * R; i += stride)
+      gstatus[(size_t)p * gstatus_pass_stride + i] = 0;
+  }
+}
+
 template <typename K, int DB, int KPT>
 __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__ keys, const SortHdr* hdr,
                                                            const SortSeg* __restrict__ segs, uint32_t passes,
@@ -160,16 +191,6 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
   uint32_t* const lane_h = s_h + (threadIdx.x % kHistLaneCopies) * kStride;
   for (uint32_t i = threadIdx.x; i < kHistLaneCopies * kStride; i += kSortThreads) s_h[i] = 0;
   __syncthreads();
-  // the count of word i over the lane copies, which are cleared for reuse
-  auto take = [&](uint32_t i) {
-    uint32_t v = 0;
-#pragma unroll
-    for (uint32_t c = 0; c < kHistLaneCopies; ++c) {
-      v += s_h[c * kStride + i];
-      s_h[c * kStride + i] = 0;
-    }
-    return v;
-  };
   const uint32_t u0 = (uint32_t)(((uint64_t)blockIdx.x * U) / gridDim.x);
   const uint32_t u1 = (uint32_t)(((uint64_t)(blockIdx.x + 1) * U) / gridDim.x);
   uint32_t cur = u0 < u1 ? seg_of_tile(segs, nseg, u0 / kUnitsPerTile) : 0u;
@@ -179,10 +200,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
     while (s + 1 < nseg && segs[s + 1].tile_off <= t) ++s;  // block-uniform
     if (s != cur) {
       __syncthreads();
-      for (uint32_t i = threadIdx.x; i < words; i += kSortThreads) {
-        const uint32_t v = take(i);
-        if (v) atomicAdd(&hist[((size_t)cur * copies + copy) * words + i], v);
-      }
+      flush_lane_hist(s_h, kStride, words, hist + ((size_t)cur * copies + copy) * words);
       __syncthreads();
       cur = s;
     }
@@ -203,20 +221,9 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
     }
   }
   __syncthreads();
-  if (u0 < u1)
-    for (uint32_t i = threadIdx.x; i < words; i += kSortThreads) {
-      const uint32_t v = take(i);
-      if (v) atomicAdd(&hist[((size_t)cur * copies + copy) * words + i], v);
-    }
+  if (u0 < u1) flush_lane_hist(s_h, kStride, words, hist + ((size_t)cur * copies + copy) * words);
   // clear the look-back words of the tiles and groups this sort will use
-  const uint32_t stride = gridDim.x * kSortThreads;
-  const uint32_t groups = T / kGroup + nseg;
-  for (uint32_t p = 0; p < passes; ++p) {
-    for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < T * R; i += stride)
-      status[(size_t)p * status_pass_stride + i] = 0;
-    for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < groups * R; i += stride)
-      gstatus[(size_t)p * gstatus_pass_stride + i] = 0;
-  }
+  clear_lookback(status, status_pass_stride, T, gstatus, gstatus_pass_stride, T / kGroup + nseg, passes, R);
 }
 
 // The keys of a dense single-segment sort computed and counted in one pass
@@ -266,20 +273,8 @@ __global__ __launch_bounds__(kSortThreads) void k_keys_hist(const float4* __rest
     }
   }
   __syncthreads();
-  if (u0 < u1)
-    for (uint32_t i = threadIdx.x; i < words; i += kSortThreads) {
-      uint32_t v = 0;
-#pragma unroll
-      for (uint32_t c = 0; c < kHistLaneCopies; ++c) v += s_h[c * kStride + i];
-      if (v) atomicAdd(&hist[(size_t)copy * words + i], v);
-    }
-  const uint32_t stride = gridDim.x * kSortThreads;
-  for (uint32_t p = 0; p < passes; ++p) {
-    for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < status_tiles * R; i += stride)
-      status[(size_t)p * status_pass_stride + i] = 0;
-    for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < status_groups * R; i += stride)
-      gstatus[(size_t)p * gstatus_pass_stride + i] = 0;
-  }
+  if (u0 < u1) flush_lane_hist(s_h, kStride, words, hist + (size_t)copy * words);
+  clear_lookback(status, status_pass_stride, status_tiles, gstatus, gstatus_pass_stride, status_groups, passes, R);
 }
 
 template <typename K, int DB, int KPT>
