@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--skip", default="", help="comma list of sections to skip: " + ",".join(SECTIONS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
                     help="offered loads, fractions of the measured batched capacity")
     ap.add_argument("--phases", default="all", choices=["all", "trace", "trace4m", "sort", "batch"],
@@ -239,6 +239,7 @@ def main():
                      "separate_calls_total": round(keys_ms + sort_ms + gather_ms + trace_ms, 4)},
         "sort_gbs": round(sort_bytes / (sort_ms * 1e-3) / 1e9, 1),
         "sort_roofline_frac": round(sort_bytes / (sort_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
+        "hbm_copy_gbs": copy_bandwidth(torch, dev, stream),
         "simd_efficiency": {"sorted": round(prof["simd_efficiency"], 3),
                             "unsorted": round(uprof["simd_efficiency"], 3)},
         "per_ray": {"inner_visits": round(prof["inner_visits"] / n, 2), "leaf_visits": round(prof["leaf_visits"] / n, 2),
@@ -543,7 +544,7 @@ BATCH_PROFILE_SHAPE = {"digit_bits": 8, "keys_per_thread": 8, "refill": 8, "tile
 def batch_only(torch, rr, W, scene, w, dev, args):
     """For profiler runs: the 64-wavefront batch graph in BATCH_PROFILE_SHAPE,
     warmup + steps launches."""
-    segs, keep, total = batch_segments(torch, rr, W, scene, w, dev)
+    segs, keep, total, _ = batch_segments(torch, rr, W, scene, w, dev)
     with rr.Batch(scene, max_rays=total, max_segments=len(segs), config=BATCH_PROFILE_SHAPE) as b:
         for _ in range(args.warmup + args.steps):
             b.run(segs, flags=0)
@@ -696,7 +697,7 @@ def batch_segments(torch, rr, W, scene, w, dev):
     """The 64 wavefronts of the batched section: sizes log-uniform in
     [4K, 2M], each drawn from the primary or bounce 1-4 rays of the 1920x1080
     city view, Two Point 64-bit keys.  Returns (segments, tensors kept alive,
-    total rays)."""
+    total rays, the key parameters)."""
     c = w.city
     pools = []
     r = W.camera_rays(4, 1920, 1080, (c.nx / 2.0, 0.6 * max(c.nx, c.nz), c.nz / 2.0))
@@ -717,13 +718,13 @@ def batch_segments(torch, rr, W, scene, w, dev):
         hits = torch.empty((int(m), 4), dtype=torch.float32, device=dev)
         keep.append((rays, hits))
         segs.append(rr.segment(rays, hits, key))
-    return segs, keep, int(sizes.sum())
+    return segs, keep, int(sizes.sum()), key
 
 
 def batched(torch, rr, W, scene, w, dev, stream):
     """The 64 wavefronts reordered and traced in one graph launch (shape
     from the autotuner), against the same wavefronts one call each."""
-    segs, keep, total = batch_segments(torch, rr, W, scene, w, dev)
+    segs, keep, total, key = batch_segments(torch, rr, W, scene, w, dev)
     out = {"segments": len(segs), "rays": total}
     with rr.Batch(scene, max_rays=total, max_segments=len(segs)) as b:
         t0 = time.perf_counter()
@@ -778,7 +779,7 @@ def served(torch, rr, W, dev, n_req, loads):
         r, alive = W.bounce(c, 5, 300 + k, r, alive)
         pools.append(torch.from_numpy(np.ascontiguousarray(r[alive.astype(bool)])).to(dev))
     kinds = ["none", "od32", "od64", "ot64"]
-    warm = 10
+    warm = 50
     reqs = []
     for i in range(n_req + warm):
         m = int(math.floor(math.exp(math.log(16384) + W.rngu(5, 50, i) * (math.log(1 << 22) - math.log(16384)))))
@@ -837,9 +838,34 @@ def cpu_baseline(w, key):
         O.reorder_and_trace(bvh, w.rays, kind, bits, lo, hi, 0.25, threads=threads)
         t.append(time.perf_counter() - t0)
     s = float(np.median(t))
-    return {"value": round(n / s / 1e6, 3), "unit": "MRays/s", "cores": threads, "kind": "oracle",
+    return {"value": round(n / s / 1e6, 3), "unit": "MRays/s", "cores": threads, "cpu": cpu_model(),
+            "kind": "oracle",
             "sample": f"the whole {n}-ray wavefront, median of 3 runs ({s:.2f} s each); keys and trace "
                       f"threaded over {threads} host threads, sort single-threaded (numpy lexsort)"}
+
+
+def copy_bandwidth(torch, dev, stream):
+    """Measured device-copy bandwidth beside the 8 TB/s vendor peak: a plain
+    1 GiB device-to-device copy, bytes read plus bytes written over its
+    median time of 5 (after one warm-up)."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    ms = median_ms(torch, stream, lambda: b.copy_(a), 5)
+    del a, b
+    return round(2 * (1 << 30) / (ms * 1e-3) / 1e9, 1)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def copy_calibration(torch, dev):
