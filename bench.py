@@ -98,8 +98,8 @@ def median_ms(torch, stream, fn, reps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              "(the path shards by ray ranges with no exchange)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the path would shard by ray ranges with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     import torch
