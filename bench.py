@@ -556,8 +556,9 @@ def batch_only(torch, rr, W, scene, w, dev, args):
 def sorts_only(torch, rr, W, dev, args):
     """For counter runs: device-wide sorts of 64-bit pairs, warmup and steps
     alike, in this order: the headline's Two Point keys (2,073,600), random
-    keys (2,073,600), random keys (8,294,400).  Each sort is one setup, one
-    histogram and 8 scatter launches."""
+    keys (2,073,600), random keys (8,294,400), random keys (67,108,864, more
+    than the 256 MB MALL holds).  Each sort is one setup, one histogram and
+    8 scatter launches."""
     w = W.bounce2_1080p()
     with rr.Scene(w.tris) as sc:
         lo, hi = sc.bounds()
@@ -569,7 +570,9 @@ def sorts_only(torch, rr, W, dev, args):
              ("random_2M", torch.randint(-(1 << 62), 1 << 62, (k_real.shape[0],), dtype=torch.int64, device=dev,
                                          generator=g)),
              ("random_8M", torch.randint(-(1 << 62), 1 << 62, (8294400,), dtype=torch.int64, device=dev,
-                                         generator=g))]
+                                         generator=g)),
+             ("random_64M", torch.randint(-(1 << 62), 1 << 62, (1 << 26,), dtype=torch.int64, device=dev,
+                                          generator=g))]
     work = []
     for name, k0 in cases:
         m = k0.shape[0]
