@@ -217,6 +217,27 @@ def test_server_results_equal_alone_and_overlap(rr, city):
         assert x["start_s"] >= x["arrival_s"] - 1e-6 and x["finish_s"] >= x["start_s"]
 
 
+def test_server_sample_against_the_oracle(rr, city):
+    """A seeded sample of 32 served requests (mixed sizes and key methods,
+    overlapping on three slots): each request's hits, in ray order, equal
+    the oracle's trace of that request bit for bit."""
+    w, scene = city
+    bvh = O.BVH(w.tris)
+    rng = np.random.default_rng(32)
+    sizes = [int(x) for x in np.exp(rng.uniform(np.log(64), np.log(20000), 32))]
+    segs = make_segments(rr, w, scene, sizes, seed=32)
+    with rr.Server(scene, slots=3, hbm_budget_bytes=8 << 30, max_batch_rays=60000, max_batch_requests=6) as sv:
+        sv.start()
+        ids = [sv.submit(s["rays"], s["hits"], s["key"], arrival_s=0.001 * k) for k, s in enumerate(segs)]
+        sv.drain(120.0)
+        st = [sv.wait(i) for i in ids]
+    assert all(x["status"] == 0 and x["done"] for x in st)
+    torch.cuda.synchronize()
+    for j, s in enumerate(segs):
+        want = bvh.trace(s["rays_np"])
+        assert rr.hits_to_numpy(s["hits"]).tobytes() == want.tobytes(), j
+
+
 def test_server_batches_and_overlaps_under_load(rr, city):
     w, scene = city
     sizes = [40000] * 16
