@@ -1,0 +1,125 @@
+"""GPU parity at the full sizes the bench times, in its launch configuration:
+the 1920x1080 bounce-2 wavefront on the ~1M-triangle grid city (2,073,600
+rays), the 3840x2160 bounce-3 wavefront on the same city (8,294,400 slots,
+compacted before the sort) and the 64-wavefront batch (17.4M rays).  Keys and
+permutations are checked in full against the oracle, hits on a seeded sample
+of sorted positions against the oracle's trace, and in full through
+properties (hits scattered back to ray order equal the unsorted trace bit
+for bit)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda"
+SAMPLE = 4096
+
+
+@pytest.fixture(scope="module")
+def rr():
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    import paper_2506_11273_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def city(rr):
+    """The headline wavefront, its scene on the device and the oracle's BVH."""
+    w = W.bounce2_1080p()
+    scene = rr.Scene(w.tris)
+    yield w, scene, O.BVH(w.tris)
+    scene.close()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def keys_np(t, bits):
+    a = t.cpu().numpy()
+    return a.view(np.uint32) if bits == 32 else a.view(np.uint64)
+
+
+def sample(n, seed):
+    return np.random.default_rng(seed).choice(n, min(n, SAMPLE), replace=False)
+
+
+@pytest.mark.parametrize("kind,bits", [(O.KIND_OT, 64), (O.KIND_OD, 64)])
+def test_headline_keys_and_fused_call(rr, city, kind, bits):
+    w, scene, bvh = city
+    lo, hi = scene.bounds()
+    n = w.rays.shape[0]
+    rays = to_dev(w.rays)
+    p = rr.key_params(kind, bits, lo, hi, 0.25)
+    want_keys = O.keys(w.rays, kind, bits, lo, hi, 0.25)
+    k, _, _ = rr.rr_compute_keys(rays, p)
+    assert np.array_equal(keys_np(k, bits), want_keys)
+    _, want_perm = O.sort_pairs(want_keys)
+    # the bench's step: keys and histograms in one kernel, the gather in the
+    # sort's last pass, hits in key order
+    hits, perm, cnt = rr.rr_reorder_and_trace(scene, rays, p, flags=0)
+    assert int(cnt.cpu().numpy()[0]) == n
+    assert np.array_equal(perm.cpu().numpy().view(np.uint32), want_perm)
+    h = rr.hits_to_numpy(hits)
+    s = sample(n, bits + kind)
+    assert h[s].tobytes() == bvh.trace(w.rays[want_perm[s]]).tobytes()
+    # hits scattered back equal the unsorted trace, every ray
+    back, _, _ = rr.rr_reorder_and_trace(scene, rays, p, flags=rr.RR_HITS_ORIGINAL_ORDER)
+    plain = rr.hits_to_numpy(rr.rr_trace(scene, rays))
+    assert rr.hits_to_numpy(back).tobytes() == plain.tobytes()
+    assert h.tobytes() == plain[want_perm].tobytes()
+
+
+def test_bounce3_compacted(rr, city):
+    w, scene, bvh = city
+    w3 = W.bounce3_2160p()
+    assert np.array_equal(w3.tris, w.tris)  # the same city
+    lo, hi = scene.bounds()
+    live = O.compact(w3.alive)
+    p = rr.key_params(O.KIND_OT, 64, lo, hi, 0.25)
+    hits, perm, cnt = rr.rr_reorder_and_trace(scene, to_dev(w3.rays), p, alive=to_dev(w3.alive), flags=0)
+    c = int(cnt.cpu().numpy()[0])
+    assert c == len(live)
+    k = O.keys(w3.rays[live], O.KIND_OT, 64, lo, hi, 0.25)
+    order = np.lexsort((live, k))
+    want_perm = live[order].astype(np.uint32)
+    assert np.array_equal(perm.cpu().numpy().view(np.uint32)[:c], want_perm)
+    h = rr.hits_to_numpy(hits)
+    s = sample(c, 3)
+    assert h[s].tobytes() == bvh.trace(w3.rays[want_perm[s]]).tobytes()
+
+
+def test_batch_64_wavefronts(rr, city):
+    """The bench's batch (its segments built by the bench's own code), in the
+    default launch shape and in the autotuner's usual one."""
+    w, scene, bvh = city
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    segs, keep, total, key = bench.batch_segments(torch, rr, W, scene, w, torch.device(DEV))
+    assert len(segs) == 64 and total > 10_000_000
+    lo, hi = scene.bounds()
+    perms = [torch.empty(r.shape[0], dtype=torch.int32, device=DEV) for r, _ in keep]
+    with_perm = [rr.segment(r, h, key, perm=q) for (r, h), q in zip(keep, perms)]
+    rays_np = [r.cpu().numpy() for r, _ in keep]
+    want = []
+    for rn in rays_np:
+        _, wp = O.sort_pairs(O.keys(rn, O.KIND_OT, 64, lo, hi, 0.25))
+        want.append(wp)
+    for shape in (None, bench.BATCH_PROFILE_SHAPE):
+        with rr.Batch(scene, max_rays=total, max_segments=len(segs), config=shape) as b:
+            b.run(with_perm, flags=0)
+            torch.cuda.synchronize()
+        for j, ((r, h), q) in enumerate(zip(keep, perms)):
+            assert np.array_equal(q.cpu().numpy().view(np.uint32), want[j]), (shape, j)
+            s = sample(r.shape[0], 100 + j)[:256]
+            got = rr.hits_to_numpy(h)
+            assert got[s].tobytes() == bvh.trace(rays_np[j][want[j][s]]).tobytes(), (shape, j)
