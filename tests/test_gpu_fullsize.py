@@ -1,11 +1,12 @@
 """GPU parity at the full sizes the bench times, in its launch configuration:
 the 1920x1080 bounce-2 wavefront on the ~1M-triangle grid city (2,073,600
 rays), the 3840x2160 bounce-3 wavefront on the same city (8,294,400 slots,
-compacted before the sort) and the 64-wavefront batch (17.4M rays).  Keys and
-permutations are checked in full against the oracle, hits on a seeded sample
-of sorted positions against the oracle's trace, and in full through
-properties (hits scattered back to ray order equal the unsorted trace bit
-for bit)."""
+compacted before the sort), the 64-wavefront batch (17.4M rays) and the
+served configuration on the ~4M-triangle city (requests of 16K to 4M rays).
+Keys and permutations are checked in full against the oracle, hits on a
+seeded sample of sorted positions against the oracle's trace, and in full
+through properties (hits scattered back to ray order equal the unsorted trace
+bit for bit)."""
 import os
 import sys
 
@@ -123,3 +124,39 @@ def test_batch_64_wavefronts(rr, city):
             s = sample(r.shape[0], 100 + j)[:256]
             got = rr.hits_to_numpy(h)
             assert got[s].tobytes() == bvh.trace(rays_np[j][want[j][s]]).tobytes(), (shape, j)
+
+
+def test_served_4m_city(rr):
+    """The serving configuration of the bench (~4M-triangle city, requests
+    of 16K to 4M rays with mixed key methods, two slots, 32 GB budget): every
+    served hit equals the unsorted trace of its request, and a sample of 512
+    per request equals the oracle's trace."""
+    c = W.city(5, 200, 200, 3_520_000)
+    r = W.camera_rays(5, 3840, 2160, (100.0, 120.0, 100.0))
+    r, alive = W.bounce(c, 5, 300, r, np.ones(r.shape[0], np.uint8))
+    pool = np.ascontiguousarray(r[alive.astype(bool)])
+    bvh = O.BVH(c.tris)
+    sizes = [16384, 100_000, 500_000, 1_000_000, 2_000_000, 1 << 22]
+    kinds = [(0, 32), (1, 32), (1, 64), (2, 64)]
+    with rr.Scene(c.tris) as scene:
+        lo, hi = scene.bounds()
+        reqs = []
+        for j, n in enumerate(sizes):
+            ix = W.sample_indices(5, 7000 + j, n, pool.shape[0])
+            rn = np.ascontiguousarray(pool[ix])
+            kind, bits = kinds[j % len(kinds)]
+            reqs.append((rn, to_dev(rn), torch.empty((n, 4), dtype=torch.float32, device=DEV),
+                         rr.key_params(kind, bits, lo, hi, 0.25)))
+        with rr.Server(scene, slots=2, hbm_budget_bytes=32 << 30, max_batch_rays=1 << 23,
+                       max_batch_requests=16) as sv:
+            sv.start()
+            ids = [sv.submit(rd, h, p, arrival_s=0.0005 * j) for j, (_, rd, h, p) in enumerate(reqs)]
+            sv.drain(300.0)
+            st = [sv.wait(i) for i in ids]
+        assert all(x["status"] == 0 and x["done"] for x in st)
+        torch.cuda.synchronize()
+        for j, (rn, rd, h, _) in enumerate(reqs):
+            got = rr.hits_to_numpy(h)
+            assert got.tobytes() == rr.hits_to_numpy(rr.rr_trace(scene, rd)).tobytes(), j
+            s = sample(rn.shape[0], 500 + j)[:512]
+            assert got[s].tobytes() == bvh.trace(rn[s]).tobytes(), j
