@@ -170,6 +170,66 @@ def test_sort_every_configuration_identical(rr, bits, digit_bits, kpt):
     assert np.array_equal(keys_np(kd, bits), ks)
 
 
+
+def _edge_keys(case, n, bits, rng):
+    """Key distributions at the ends of what the digit passes meet."""
+    top = (1 << bits) - 1
+    dt = np.uint32 if bits == 32 else np.uint64
+    if case == "all_equal":
+        return np.full(n, 0x5A5A5A5A5A5A5A5A & top, dt)
+    if case == "ascending":
+        return np.sort(rng.integers(0, top, n, dtype=np.uint64, endpoint=True).astype(dt) >> dt(3))
+    if case == "descending":
+        return np.sort(rng.integers(0, top, n, dtype=np.uint64, endpoint=True).astype(dt))[::-1].copy()
+    if case == "extremes":
+        return np.where(rng.integers(0, 2, n) == 1, dt(top), dt(0)).astype(dt)
+    if case == "low_byte_only":
+        return (rng.integers(0, 256, n, dtype=np.uint64) | np.uint64(0x1234567800000000 & top)).astype(dt)
+    if case == "top_byte_only":
+        return (rng.integers(0, 256, n, dtype=np.uint64) << np.uint64(bits - 8)).astype(dt)
+    if case == "one_hot_value":
+        k = rng.integers(0, top, n, dtype=np.uint64, endpoint=True).astype(dt)
+        k[rng.random(n) < 0.9] = dt(0x00FF00FF00FF00FF & top)
+        return k
+    raise ValueError(case)
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("case", ["all_equal", "ascending", "descending", "extremes", "low_byte_only",
+                                  "top_byte_only", "one_hot_value"])
+def test_sort_edge_distributions(rr, bits, case):
+    """Stability by input position with indices that do not ascend (reversed,
+    then a random permutation), in the default configuration and two others."""
+    n = 300007
+    rng = np.random.default_rng(bits * 100 + len(case))
+    k = _edge_keys(case, n, bits, rng)
+    _, perm = O.sort_pairs(k)  # stable order of the positions
+    ks = k[perm]
+    for idx_in, cfg in ((np.arange(n, dtype=np.uint32)[::-1].copy(), {}),
+                        (rng.permutation(n).astype(np.uint32), {"digit_bits": 8, "keys_per_thread": 16}),
+                        (rng.permutation(n).astype(np.uint32), {"digit_bits": 4, "keys_per_thread": 8})):
+        kd = to_dev(k.view(np.int32 if bits == 32 else np.int64))
+        idx = to_dev(idx_in.view(np.int32))
+        rr.rr_sort(kd, idx, **cfg)
+        assert np.array_equal(keys_np(kd, bits), ks), (case, cfg)
+        assert np.array_equal(idx_np(idx), idx_in[perm]), (case, cfg)
+
+
+def test_sort_past_2_24_with_device_count(rr):
+    """The 16-keys-per-thread configuration rr_sort takes from 2^24 keys on,
+    with a device count below the capacity and 2^20 distinct 64-bit keys."""
+    n_max, n = (1 << 24) + 4097, (1 << 24) + 1001
+    k = _random_keys(n_max, 64, 77, 44)
+    kd = to_dev(k.view(np.int64))
+    idx = torch.arange(n_max, dtype=torch.int32, device=DEV)
+    cnt = torch.tensor([n], dtype=torch.int32, device=DEV)
+    rr.rr_sort(kd, idx, count=cnt)
+    ks, ix = O.sort_pairs(k[:n])
+    got_k = keys_np(kd, 64)
+    assert np.array_equal(idx_np(idx)[:n], ix)
+    assert np.array_equal(got_k[:n], ks)
+    assert np.array_equal(got_k[n:], k[n:])
+
 def test_sort_device_count(rr):
     n_max, n = 50000, 31337
     k = _random_keys(n_max, 64, 5, 20)
