@@ -230,6 +230,7 @@ def test_sort_past_2_24_with_device_count(rr):
     assert np.array_equal(got_k[:n], ks)
     assert np.array_equal(got_k[n:], k[n:])
 
+
 def test_sort_device_count(rr):
     n_max, n = 50000, 31337
     k = _random_keys(n_max, 64, 5, 20)
@@ -330,6 +331,29 @@ def test_trace_tiny_scenes_and_ties(rr):
         with rr.Scene(T) as sc:
             h = rr.hits_to_numpy(rr.rr_trace(sc, to_dev(rays)))
         assert h.tobytes() == ref.tobytes()
+
+
+
+@pytest.mark.parametrize("scale", [1.0, 2.0 ** -40, 2.0 ** 40])
+def test_trace_degenerate_geometry(rr, scale):
+    """Zero-area and duplicate triangles, rays parallel to triangles, axis-
+    aligned and negative-zero directions, empty and inverted intervals, at
+    three scales (powers of two, so the scaled inputs are exact): hits
+    bit-identical to brute force with both builders, alone and through the
+    fused call."""
+    T, rays = W.degenerate(12, 3000, 8192, scale)
+    ref = O.brute_force(T, rays)
+    assert (ref["prim"] >= 0).sum() > 1000  # the scene is hit
+    for builder in (0, 1):
+        with rr.Scene(T, builder=builder) as sc:
+            rd = to_dev(rays)
+            h = rr.hits_to_numpy(rr.rr_trace(sc, rd))
+            assert h.tobytes() == ref.tobytes(), (scale, builder)
+            # reordered by the Two Point key, hits scattered back to ray order
+            lo, hi = sc.bounds()
+            p = rr.key_params(O.KIND_OT, 64, lo, hi, 0.25)
+            back, _, _ = rr.rr_reorder_and_trace(sc, rd, p, flags=rr.RR_HITS_ORIGINAL_ORDER)
+            assert rr.hits_to_numpy(back).tobytes() == ref.tobytes(), (scale, builder)
 
 
 # ---------------------------------------------------------- fused pipeline

@@ -158,6 +158,23 @@ def test_bvh_equals_brute_force_small_city():
     assert np.mean(bf["prim"] >= 0) > 0.5
 
 
+@pytest.mark.parametrize("scale", [1.0, 2.0 ** -40, 2.0 ** 40])
+def test_bvh_equals_brute_force_degenerate(scale):
+    """Zero-area and duplicate triangles, rays in the plane of axis-aligned
+    triangles, axis-aligned and negative-zero directions, empty and inverted
+    intervals: the BVH finds brute force's hits, bit for bit, at three
+    scales.  Scaling up by a power of two changes no hit's primitive; at
+    2^-40 products of the near-degenerate edges fall into the subnormal
+    range, lose precision, and a few hits may change."""
+    T, rays = W.degenerate(12, 3000, 8192, scale)
+    bf = O.brute_force(T, rays)
+    assert O.BVH(T).trace(rays).tobytes() == bf.tobytes()
+    assert (bf["prim"] >= 0).sum() > 1000
+    if scale >= 1.0:
+        T1, rays1 = W.degenerate(12, 3000, 8192, 1.0)
+        assert np.array_equal(bf["prim"], O.brute_force(T1, rays1)["prim"])
+
+
 def test_bvh_indirect_equals_gather():
     w = W.soup(seed=4, n_rays=4000, n_tris=500)
     bvh = O.BVH(w.tris)

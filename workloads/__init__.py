@@ -229,6 +229,60 @@ def segment_sizes(seed: int, count: int = 64, lo: int = 4096, hi: int = 1 << 21)
     return np.floor(np.exp(math.log(lo) + u * (math.log(hi) - math.log(lo)))).astype(np.int64)
 
 
+
+def _degenerate_scene(rng, n: int) -> np.ndarray:
+    """n triangles in the unit cube: a tenth with two equal vertices, a tenth
+    with collinear vertices, a tenth exact copies of earlier ones, a tenth
+    axis-aligned in the plane z = 0.5, the rest random."""
+    T = rng.random((n, 9)).astype(np.float32)
+    k = n // 10
+    T[0:k, 3:6] = T[0:k, 0:3]                                   # repeated vertex
+    mid = rng.random((k, 1)).astype(np.float32)
+    T[k:2 * k, 6:9] = T[k:2 * k, 0:3] + mid * (T[k:2 * k, 3:6] - T[k:2 * k, 0:3])  # collinear
+    T[2 * k:3 * k] = T[rng.integers(3 * k, n, k)]               # duplicates (later ids)
+    T[3 * k:4 * k, 2::3] = np.float32(0.5)                      # in the plane z = 0.5
+    return T
+
+
+def _degenerate_rays(rng, n: int) -> np.ndarray:
+    """Rays with axis-aligned directions (zero and negative-zero components),
+    rays in the plane z = 0.5 (parallel to the axis-aligned triangles), empty
+    and inverted intervals, origins on that plane, and negative tmin."""
+    o = rng.random((n, 3)).astype(np.float32) * np.float32(1.4) - np.float32(0.2)
+    d = rng.normal(size=(n, 3)).astype(np.float32)
+    q = n // 8
+    axis = rng.integers(0, 3, q)
+    d[:q] = 0.0
+    d[np.arange(q), axis] = np.where(rng.random(q) < 0.5, -1.0, 1.0)
+    d[:q:2][d[:q:2] == 0] = -0.0                                # negative zeros
+    o[q:2 * q, 2] = np.float32(0.5)
+    d[q:2 * q, 2] = 0.0                                         # in the plane z = 0.5
+    o[2 * q:3 * q, 2] = np.float32(0.5)                         # starting on the plane
+    d /= np.linalg.norm(d, axis=1, keepdims=True).astype(np.float32)
+    tmin = np.zeros(n, np.float32)
+    tmax = np.full(n, np.inf, np.float32)
+    tmin[3 * q:3 * q + q // 2] = np.float32(0.3)
+    tmax[3 * q:3 * q + q // 2] = np.float32(0.3)                # empty interval
+    tmin[3 * q + q // 2:4 * q] = np.float32(2.0)
+    tmax[3 * q + q // 2:4 * q] = np.float32(1.0)                # inverted interval
+    tmin[4 * q:5 * q] = np.float32(-1.0)                        # hits behind the origin count
+    return np.ascontiguousarray(np.concatenate([o, tmin[:, None], d, tmax[:, None]], axis=1), np.float32)
+
+
+def degenerate(seed: int, n_tris: int, n_rays: int, scale: float = 1.0):
+    """Triangles and rays at the degenerate ends of the closest-hit test,
+    scaled by `scale` (a power of two keeps every scaled value exact)."""
+    rng = np.random.default_rng(seed)
+    T = _degenerate_scene(rng, n_tris)
+    rays = _degenerate_rays(rng, n_rays)
+    s = np.float32(scale)
+    T = T * s
+    rays[:, 0:3] *= s
+    rays[:, 3] *= s
+    rays[:, 7] *= s
+    return T, rays
+
+
 def sample_indices(seed: int, stream: int, n: int, pool: int) -> np.ndarray:
     """n indices drawn with replacement from range(pool)."""
     out = np.empty(n, np.int64)
