@@ -126,15 +126,16 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_out(const BatchHdr* __res
   }
 }
 
+// Grid of the streaming kernels: 8 blocks per CU, queried once (thread-safe
+// static initialisation: the server's thread launches batches too).
 uint32_t streaming_blocks() {
-  static uint32_t v = 0;
-  if (!v) {
+  static const uint32_t v = [] {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
       cus = 256;
-    v = (uint32_t)cus * 8;
-  }
+    return (uint32_t)cus * 8;
+  }();
   return v;
 }
 

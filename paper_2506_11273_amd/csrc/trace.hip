@@ -389,19 +389,22 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
 
 constexpr int kTraceBlock = 256;
 
+// Blocks of one resident wave of the grid, queried once per instance (a
+// function-local static, so a server thread and the caller's thread may
+// both ask).
 template <int BLOCK, bool STATS, bool QNODE, bool ANY>
 uint32_t resident_blocks() {
-  static uint32_t cached = 0;
-  if (cached) return cached;
-  int dev = 0, cus = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-    cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace4<BLOCK, STATS, QNODE, ANY>, BLOCK, 0) !=
-          hipSuccess ||
-      per <= 0)
-    per = 1024 / BLOCK;
-  cached = (uint32_t)(cus * per);
+  static const uint32_t cached = [] {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace4<BLOCK, STATS, QNODE, ANY>, BLOCK, 0) !=
+            hipSuccess ||
+        per <= 0)
+      per = 1024 / BLOCK;
+    return (uint32_t)(cus * per);
+  }();
   return cached;
 }
 
