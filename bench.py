@@ -49,7 +49,7 @@ TRAFFIC_SOURCES = ("paper_2506_11273_amd/csrc/trace.hip", "paper_2506_11273_amd/
 SECTIONS = ("variants", "orders", "shuffled", "shadow", "bounce3", "sorts", "batch", "serve", "cpu")
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -69,8 +69,11 @@ def parse():
                          "batch graph in a fixed launch shape (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
-    a = ap.parse_args()
+    a = ap.parse_args(argv)
     a.skip = set(s for s in a.skip.split(",") if s)
+    unknown = sorted(a.skip - set(SECTIONS))
+    if unknown:
+        ap.error(f"--skip: unknown section(s) {','.join(unknown)}; known: {','.join(SECTIONS)}")
     if a.no_cpu_baseline:
         a.skip.add("cpu")
     if a.no_variants:

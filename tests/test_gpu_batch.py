@@ -238,6 +238,44 @@ def test_server_sample_against_the_oracle(rr, city):
         assert rr.hits_to_numpy(s["hits"]).tobytes() == want.tobytes(), j
 
 
+def test_direct_calls_beside_a_busy_server(rr, city):
+    """The caller's own fused calls and batches, on a stream of its own,
+    while the server's thread runs batches on its streams: both give the
+    results each gives alone (the per-call sort waits through its bounded
+    look-back fallback when the server holds CUs)."""
+    w, scene = city
+    lo, hi = scene.bounds()
+    rng = np.random.default_rng(41)
+    sizes = [int(x) for x in np.exp(rng.uniform(np.log(2000), np.log(80000), 24))]
+    segs = make_segments(rr, w, scene, sizes, seed=41)
+    direct = to_dev(w.rays[:150001])
+    p = rr.key_params(O.KIND_OT, 64, lo, hi, 0.25)
+    want_direct = rr.hits_to_numpy(rr.rr_reorder_and_trace(scene, direct, p, flags=rr.RR_HITS_ORIGINAL_ORDER)[0])
+    own = make_segments(rr, w, scene, [3000, 40000, 777], seed=42)
+    own_structs = seg_structs(rr, own)
+    side = torch.cuda.Stream()
+    with rr.Server(scene, slots=2, hbm_budget_bytes=8 << 30, max_batch_rays=120000, max_batch_requests=8) as sv, \
+            rr.Batch(scene, max_rays=50000, max_segments=4) as b:
+        sv.start()
+        ids = [sv.submit(s["rays"], s["hits"], s["key"], arrival_s=0.0005 * k) for k, s in enumerate(segs)]
+        got = []
+        with torch.cuda.stream(side):
+            for _ in range(6):
+                h, _, _ = rr.rr_reorder_and_trace(scene, direct, p, flags=rr.RR_HITS_ORIGINAL_ORDER)
+                b.run(own_structs)
+                got.append(h)
+        side.synchronize()
+        sv.drain(120.0)
+        st = [sv.wait(i) for i in ids]
+    assert all(x["status"] == 0 and x["done"] for x in st)
+    for h in got:
+        assert rr.hits_to_numpy(h).tobytes() == want_direct.tobytes()
+    check(rr, scene, own, "own batch")
+    for j, s in enumerate(segs):
+        hits, _ = expected(rr, scene, s)
+        assert rr.hits_to_numpy(s["hits"]).tobytes() == hits.tobytes(), j
+
+
 def test_server_batches_and_overlaps_under_load(rr, city):
     w, scene = city
     sizes = [40000] * 16
