@@ -42,8 +42,8 @@ typedef int32_t rr_status;
 #define RR_ERR_WORKSPACE_TOO_SMALL (-5)
 #define RR_ERR_BUDGET (-6)
 
-/* Largest ray count a single call accepts (the sort's tile status words hold
- * 30-bit counts). */
+/* Bound on the ray count of a single call: calls accept n < RR_MAX_RAYS, so
+ * at most 2^30 - 1 rays (the sort's tile status words hold 30-bit counts). */
 #define RR_MAX_RAYS ((int64_t)1 << 30)
 
 /* A ray (Section 3: origin, direction and extent), 32 bytes, 16-byte
