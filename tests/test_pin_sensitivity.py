@@ -98,3 +98,60 @@ def test_each_planted_mistake_fails_a_pin(mistake):
         return mt_planted(r, t, mistake)
     passes = closed_form_ok(mt) and solve_ok(mt)
     assert passes == (mistake == "none"), mistake
+
+
+# ------------------------------------------------------------------ sort
+# The same for the sort pins: plausible mistakes in a (key, index) pair sort
+# (numpy, test-local) must fail the checks the oracle's sort passes (Python's
+# sorted() on tuples for 32-bit keys; order, permutation, stability and key
+# consistency for 64-bit keys with the top bit in use).
+
+SORT_MISTAKES = ["none", "unstable", "descending", "index_first", "signed_view", "low_32_bits_only",
+                 "index_not_moved"]
+
+
+def sort_planted(k, idx, mistake):
+    k = np.asarray(k)
+    idx = np.arange(k.shape[0], dtype=np.uint32) if idx is None else np.asarray(idx, np.uint32)
+    if mistake == "unstable":
+        order = np.argsort(k, kind="quicksort")[::-1]
+        order = order[np.argsort(k[order], kind="stable")]  # equal keys in reversed input order
+    elif mistake == "descending":
+        order = np.lexsort((idx, k))[::-1]
+    elif mistake == "index_first":
+        order = np.lexsort((k, idx))
+    elif mistake == "signed_view":
+        order = np.lexsort((idx, k.view(np.int64 if k.dtype == np.uint64 else np.int32)))
+    elif mistake == "low_32_bits_only":
+        order = np.lexsort((idx, k & np.array(0xFFFFFFFF, k.dtype)))
+    else:
+        order = np.lexsort((idx, k))
+    if mistake == "index_not_moved":
+        return k[order], idx
+    return k[order], idx[order]
+
+
+def sort_pins_ok(sort_pairs) -> bool:
+    rng = np.random.default_rng(0)
+    for n, hi in ((7, 3), (300, 16), (1000, 1 << 32)):
+        k = rng.integers(0, hi, n, dtype=np.uint64).astype(np.uint32)
+        idx = np.arange(n, dtype=np.uint32)
+        ks, ix = sort_pairs(k, idx)
+        ref = sorted(zip(k.tolist(), idx.tolist()))
+        if ks.tolist() != [a for a, _ in ref] or ix.tolist() != [b for _, b in ref]:
+            return False
+    n = 20000
+    k = rng.integers(0, 1 << 12, n, dtype=np.uint64) << np.uint64(52)  # top bit used, many equal keys
+    ks, ix = sort_pairs(k, None)
+    eq = ks[1:] == ks[:-1]
+    return bool(np.all(ks[1:] >= ks[:-1]) and np.array_equal(np.sort(ix), np.arange(n, dtype=np.uint32))
+                and np.all(ix[1:][eq] > ix[:-1][eq]) and np.array_equal(k[ix], ks))
+
+
+def test_the_oracle_sort_passes_the_pins():
+    assert sort_pins_ok(O.sort_pairs)
+
+
+@pytest.mark.parametrize("mistake", SORT_MISTAKES)
+def test_each_planted_sort_mistake_fails_a_pin(mistake):
+    assert sort_pins_ok(lambda k, i: sort_planted(k, i, mistake)) == (mistake == "none"), mistake
