@@ -20,8 +20,10 @@
  *  - n = 0 is valid and enqueues nothing (except that count outputs are
  *    written as 0).
  *  - Buffers given to one call must not overlap unless stated otherwise.
- *  - The library allocates device memory only in rr_scene_create (owned by
- *    the scene) and for its own small per-device state on first use.
+ *  - The functions of this header allocate device memory only in
+ *    rr_scene_create (owned by the scene, freed by rr_scene_destroy);
+ *    rr_batch_create and rr_server_create (rr_batch.h) allocate the buffers
+ *    of a batch.  Everything else works in caller-provided memory.
  */
 #ifndef RR_H
 #define RR_H
@@ -287,11 +289,15 @@ rr_status rr_trace_ex(rr_scene s, const rr_ray* rays, int64_t n_max, const uint3
 
 /* Profiling variant of rr_trace (Section 4.2 compares the control-flow
  * efficiency of the trace kernel on sorted and unsorted rays): same hits,
- * plus six device uint64 counters written to stats_dev (overwritten):
+ * plus RR_TRACE_PROFILE_COUNTERS device uint64 counters written to stats_dev
+ * (overwritten):
  *   [0] loop trips summed over rays, [1] loop trips of each wavefront x 64
  *       summed over wavefronts (so [0]/[1] is the SIMD efficiency),
- *   [2] inner-node visits, [3] leaf visits, [4] triangle tests, [5] rays.
+ *   [2] inner-node visits, [3] leaf visits, [4] triangle tests, [5] rays,
+ *   [6] the deepest traversal stack any ray reached (entries),
+ *   [7] stack pushes beyond the 16 entries held in LDS (into scratch).
  * Slower than rr_trace (global atomics); for measurement only. */
+#define RR_TRACE_PROFILE_COUNTERS 8
 rr_status rr_trace_profile(rr_scene s, const rr_ray* rays, int64_t n, rr_hit* hits, uint64_t* stats_dev,
                            void* stream);
 

@@ -124,11 +124,19 @@ rr_status rr_server_create(rr_scene s, const rr_server_config* cfg, rr_server* o
 /* Starts the clock that arrival times refer to and the scheduling thread. */
 rr_status rr_server_start(rr_server sv);
 /* Queues a request (no device work in the call).  arrival_s < 0 means now.
+ * flags: RR_HITS_ORIGINAL_ORDER (hits[i] belongs to rays[i]) or 0 (hits in
+ * the request's key order); a batch holds requests of one hit order.
  * A request larger than max_batch_rays is rejected with RR_ERR_BUDGET.
- * The ray and hit buffers must stay valid until the request is done. */
+ * The rays must be complete in device memory when rr_server_submit is
+ * called: the server's streams read them without waiting for the stream
+ * that produced them.  The ray and hit buffers must stay valid until the
+ * request is done. */
 rr_status rr_server_submit(rr_server sv, const rr_ray* rays, int64_t n, const rr_key_params* key, rr_hit* hits,
                            uint32_t flags, double arrival_s, int64_t* id);
-/* Blocks until the request is done (or timeout_s passes: RR_ERR_DEVICE). */
+/* Blocks until the request is done (or timeout_s passes: RR_ERR_DEVICE).
+ * rr_server_destroy fails every request not yet launched, waits for the
+ * launched ones, and returns only after every thread blocked in
+ * rr_server_wait or rr_server_drain has returned. */
 rr_status rr_server_wait(rr_server sv, int64_t id, double timeout_s, rr_request_stats* out);
 /* Blocks until every submitted request is done. */
 rr_status rr_server_drain(rr_server sv, double timeout_s);

@@ -180,12 +180,19 @@ class Server:
     def start(self):
         _check(load().rr_server_start(self.handle), "rr_server_start")
 
-    def submit(self, rays, hits, key: KeyParams, arrival_s: float = -1.0) -> int:
+    def submit(self, rays, hits, key: KeyParams, arrival_s: float = -1.0,
+               flags: int = _rr.RR_HITS_ORIGINAL_ORDER, sync: bool = True) -> int:
+        """Queues a request.  The server's streams read the rays without
+        waiting for the stream that wrote them, so by default the current
+        stream is synchronised first (pass sync=False when the rays are
+        known to be complete)."""
         import torch
+        if sync:
+            torch.cuda.current_stream().synchronize()
         rid = ctypes.c_int64()
         _check(load().rr_server_submit(self.handle, _ptr(rays, "rays", torch.float32), int(rays.shape[0]),
                                        ctypes.byref(key), _ptr(hits, "hits", torch.float32),
-                                       _rr.RR_HITS_ORIGINAL_ORDER, float(arrival_s), ctypes.byref(rid)),
+                                       int(flags), float(arrival_s), ctypes.byref(rid)),
                "rr_server_submit")
         self._keep[rid.value] = (rays, hits)
         return rid.value

@@ -332,7 +332,7 @@ rr_status rr_trace_profile(rr_scene s, const rr_ray* rays, int64_t n, rr_hit* hi
                            void* stream) {
   if (!s || !valid_n(n)) return RR_ERR_INVALID_ARGUMENT;
   if (!is_device_ptr(stats_dev) || !aligned(stats_dev, 8)) return RR_ERR_INVALID_ARGUMENT;
-  rr_status r = launch_fill_u32(reinterpret_cast<uint32_t*>(stats_dev), 12, 0u, S(stream));
+  rr_status r = launch_fill_u32(reinterpret_cast<uint32_t*>(stats_dev), 2 * RR_TRACE_PROFILE_COUNTERS, 0u, S(stream));
   if (r != RR_OK || n == 0) return r;
   if (!is_device_ptr(rays) || !is_device_ptr(hits) || !aligned(rays, 16) || !aligned(hits, 16))
     return RR_ERR_INVALID_ARGUMENT;

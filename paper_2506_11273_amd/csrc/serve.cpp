@@ -34,6 +34,7 @@ struct Req {
   const rr_ray* rays = nullptr;
   rr_hit* hits = nullptr;
   rr_key_params key{};
+  uint32_t flags = 0;  // hit order: RR_HITS_ORIGINAL_ORDER or key order
   int64_t bytes = 0;
 };
 
@@ -58,6 +59,8 @@ struct rr_server_s {
   std::mutex mu;
   std::condition_variable cv;     // wakes the loop (new request, shutdown)
   std::condition_variable done_cv;  // wakes waiters
+  std::condition_variable gone_cv;  // wakes rr_server_destroy when the last waiter has left
+  int32_t waiters = 0;              // threads inside rr_server_wait / rr_server_drain
   std::deque<int64_t> pending;    // ids in arrival order
   std::unordered_map<int64_t, Req> reqs;
   int64_t next_id = 1;
@@ -129,11 +132,16 @@ void run_loop(rr_server sv) {
     for (Slot& s : sv->slots) {
       if (s.busy || sv->stop) continue;
       int64_t rays = 0;
+      uint32_t flags = 0;
       segs.clear();
       while (!sv->pending.empty() && (int32_t)segs.size() < sv->cfg.max_batch_requests) {
         Req& r = sv->reqs[sv->pending.front()];
         if (r.st.arrival_s > t) break;  // not yet arrived
         if (rays + r.st.n > sv->cfg.max_batch_rays) break;
+        // one hit order per batch: a request asking for the other order
+        // starts the next batch
+        if (!segs.empty() && r.flags != flags) break;
+        flags = r.flags;
         segs.push_back(rr_segment{r.rays, r.hits, nullptr, r.st.n, r.key});
         s.reqs.push_back(r.st.id);
         s.bytes += r.bytes;
@@ -141,7 +149,7 @@ void run_loop(rr_server sv) {
         sv->pending.pop_front();
       }
       if (segs.empty()) continue;
-      rr_status st = rr_batch_run(s.batch, segs.data(), (int32_t)segs.size(), RR_HITS_ORIGINAL_ORDER, s.stream);
+      rr_status st = rr_batch_run(s.batch, segs.data(), (int32_t)segs.size(), flags, s.stream);
       if (st == RR_OK && hipEventRecord(s.done, s.stream) != hipSuccess) st = RR_ERR_DEVICE;
       const double ts = now_s(sv);
       for (int64_t id : s.reqs) {
@@ -277,6 +285,7 @@ rr_status rr_server_submit(rr_server sv, const rr_ray* rays, int64_t n, const rr
   r.rays = rays;
   r.hits = hits;
   r.key = *key;
+  r.flags = flags;
   r.bytes = (int64_t)(sv->bytes_per_ray * (double)n);
   sv->reqs[r.st.id] = r;
   insert_by_arrival(sv, r.st.id);
@@ -285,9 +294,21 @@ rr_status rr_server_submit(rr_server sv, const rr_ray* rays, int64_t n, const rr
   return RR_OK;
 }
 
+// Counts a thread inside rr_server_wait / rr_server_drain (under the
+// mutex), so that rr_server_destroy frees the server only after every such
+// thread has left it.
+struct WaiterGuard {
+  rr_server sv;
+  explicit WaiterGuard(rr_server s) : sv(s) { ++sv->waiters; }
+  ~WaiterGuard() {
+    if (--sv->waiters == 0) sv->gone_cv.notify_all();
+  }
+};
+
 rr_status rr_server_wait(rr_server sv, int64_t id, double timeout_s, rr_request_stats* out) {
   if (!sv) return RR_ERR_INVALID_ARGUMENT;
   std::unique_lock<std::mutex> lk(sv->mu);
+  WaiterGuard guard(sv);  // destroyed before lk, with the mutex held
   auto it = sv->reqs.find(id);
   if (it == sv->reqs.end()) return RR_ERR_INVALID_ARGUMENT;
   const auto deadline = clk::now() + std::chrono::duration_cast<clk::duration>(std::chrono::duration<double>(timeout_s));
@@ -301,6 +322,7 @@ rr_status rr_server_wait(rr_server sv, int64_t id, double timeout_s, rr_request_
 rr_status rr_server_drain(rr_server sv, double timeout_s) {
   if (!sv) return RR_ERR_INVALID_ARGUMENT;
   std::unique_lock<std::mutex> lk(sv->mu);
+  WaiterGuard guard(sv);
   const auto deadline = clk::now() + std::chrono::duration_cast<clk::duration>(std::chrono::duration<double>(timeout_s));
   auto all_done = [&] {
     for (auto& kv : sv->reqs)
@@ -365,7 +387,13 @@ rr_status rr_server_destroy(rr_server sv) {
       sv->reqs[id].st.status = RR_ERR_DEVICE;
     }
     sv->pending.clear();
+  }
+  {
+    // every request is done now: threads still in rr_server_wait or
+    // rr_server_drain return; the server is freed only after they have left
+    std::unique_lock<std::mutex> lk(sv->mu);
     sv->done_cv.notify_all();
+    sv->gone_cv.wait(lk, [&] { return sv->waiters == 0; });
   }
   int cur = 0;
   (void)hipGetDevice(&cur);

@@ -62,9 +62,11 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 
 // Counters of the profiling variant (Section 4.2 profiles control-flow
 // efficiency): active lane iterations, wave iterations x 64, inner-node
-// visits, leaf visits, triangle tests, rays.
+// visits, leaf visits, triangle tests, rays; then the deepest traversal
+// stack any ray reached and the number of pushes that went to the scratch
+// part of the stack (entries beyond the LDS part).
 struct TraceStats {
-  unsigned long long lane_trips, wave_trips64, inner, leaves, tri_tests, rays;
+  unsigned long long lane_trips, wave_trips64, inner, leaves, tri_tests, rays, max_depth, spill_pushes;
 };
 
 struct Ray {
@@ -179,6 +181,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
   float tbest = 0.0f, bu = 0.0f, bv = 0.0f;
   int32_t bprim = -1;
   unsigned long long st_trips = 0, st_wave = 0, st_inner = 0, st_leaf = 0, st_tri = 0, st_rays = 0;
+  unsigned long long st_depth = 0, st_spill = 0;
 
   while (true) {
     // ---- refill idle lanes from the wave's packets (wave-uniform decision)
@@ -302,10 +305,12 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
             if (k + 1 < m) {
               if (sp < kLdsStack) lstack[sp * BLOCK] = cs[k];
               else spill[sp - kLdsStack] = cs[k];
+              if (STATS && sp >= kLdsStack) ++st_spill;
               ++sp;
             }
           }
         }
+        if (STATS && (unsigned long long)sp > st_depth) st_depth = (unsigned long long)sp;
         node = c0;
       } else {
         node = pop_or_none();
@@ -384,6 +389,8 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
     atomicAdd(&stats->tri_tests, st_tri);
     atomicAdd(&stats->rays, st_rays);
     atomicAdd(&stats->wave_trips64, 64ull * st_wave);
+    atomicMax(&stats->max_depth, st_depth);
+    atomicAdd(&stats->spill_pushes, st_spill);
   }
 }
 

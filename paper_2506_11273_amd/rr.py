@@ -414,12 +414,13 @@ def rr_trace_profile(scene: Scene, rays, hits=None, stream=None) -> dict:
     torch = _torch()
     n = _n_rows(rays)
     hits = torch.empty((n, 4), dtype=torch.float32, device=rays.device) if hits is None else hits
-    st = torch.zeros(6, dtype=torch.int64, device=rays.device)
+    st = torch.zeros(8, dtype=torch.int64, device=rays.device)
     _check(load().rr_trace_profile(scene.handle, _ptr(rays, "rays", torch.float32), n,
                                    _ptr(hits, "hits", torch.float32), _ptr(st, "stats", torch.int64),
                                    _stream(stream)), "rr_trace_profile")
     v = [int(x) for x in st.cpu().tolist()]
-    keys = ("lane_trips", "wave_trips64", "inner_visits", "leaf_visits", "tri_tests", "rays")
+    keys = ("lane_trips", "wave_trips64", "inner_visits", "leaf_visits", "tri_tests", "rays", "max_stack",
+            "spill_pushes")
     out = dict(zip(keys, v))
     out["simd_efficiency"] = v[0] / v[1] if v[1] else 0.0
     return out

@@ -323,3 +323,55 @@ def test_server_admission_and_rejection(rr, city):
     for s in (segs[0], segs[2]):
         hits, _ = expected(rr, scene, s)
         assert rr.hits_to_numpy(s["hits"]).tobytes() == hits.tobytes()
+
+
+def test_server_hit_order_per_request(rr, city):
+    """Requests asking for hits in key order (flags 0) and in ray order,
+    interleaved: each batch holds one hit order, and every request gets its
+    own order (key order = the ray-order hits permuted by the oracle's stable
+    order)."""
+    w, scene = city
+    rng = np.random.default_rng(51)
+    sizes = [int(x) for x in np.exp(rng.uniform(np.log(300), np.log(30000), 16))]
+    segs = make_segments(rr, w, scene, sizes, seed=51)
+    with rr.Server(scene, slots=2, hbm_budget_bytes=8 << 30, max_batch_rays=100000, max_batch_requests=8) as sv:
+        sv.start()
+        ids = [sv.submit(s["rays"], s["hits"], s["key"], arrival_s=0.0003 * k,
+                         flags=0 if k % 2 else rr.RR_HITS_ORIGINAL_ORDER) for k, s in enumerate(segs)]
+        sv.drain(120.0)
+        st = [sv.wait(i) for i in ids]
+    assert all(x["status"] == 0 and x["done"] for x in st)
+    for k, s in enumerate(segs):
+        hits, perm = expected(rr, scene, s)
+        want = hits[perm] if k % 2 else hits
+        assert rr.hits_to_numpy(s["hits"]).tobytes() == want.tobytes(), k
+
+
+def test_server_destroy_releases_waiting_threads(rr, city):
+    """rr_server_destroy while other threads block in rr_server_wait on
+    requests that never start (the loop was not started): every waiter
+    returns with a failure status before the server is freed."""
+    import threading
+    w, scene = city
+    segs = make_segments(rr, w, scene, [1000, 2000, 3000], seed=52)
+    sv = rr.Server(scene, slots=1, hbm_budget_bytes=8 << 30, max_batch_rays=10000)
+    ids = [sv.submit(s["rays"], s["hits"], s["key"], arrival_s=0.0) for s in segs]
+    out = {}
+
+    def waiter(i):
+        try:
+            sv.wait(i, timeout_s=30.0)
+            out[i] = "ok"
+        except rr.RRError as e:
+            out[i] = e.status
+
+    th = [threading.Thread(target=waiter, args=(i,)) for i in ids]
+    for t in th:
+        t.start()
+    import time
+    time.sleep(0.2)
+    sv.close()
+    for t in th:
+        t.join(10.0)
+    assert all(not t.is_alive() for t in th)
+    assert sorted(out) == sorted(ids) and all(v != "ok" for v in out.values())

@@ -3,10 +3,9 @@ the 1920x1080 bounce-2 wavefront on the ~1M-triangle grid city (2,073,600
 rays), the 3840x2160 bounce-3 wavefront on the same city (8,294,400 slots,
 compacted before the sort), the 64-wavefront batch (17.4M rays) and the
 served configuration on the ~4M-triangle city (requests of 16K to 4M rays).
-Keys and permutations are checked in full against the oracle, hits on a
-seeded sample of sorted positions against the oracle's trace, and in full
-through properties (hits scattered back to ray order equal the unsorted trace
-bit for bit)."""
+Keys, permutations and every hit are checked against the oracle (hits with
+the near-tie rule), and hits scattered back to ray order against the unsorted
+trace bit for bit."""
 import os
 import sys
 
@@ -15,12 +14,12 @@ import pytest
 
 import oracle as O
 import workloads as W
+from hitcheck import assert_hits_match
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 DEV = "cuda"
-SAMPLE = 4096
 
 
 @pytest.fixture(scope="module")
@@ -50,10 +49,6 @@ def keys_np(t, bits):
     return a.view(np.uint32) if bits == 32 else a.view(np.uint64)
 
 
-def sample(n, seed):
-    return np.random.default_rng(seed).choice(n, min(n, SAMPLE), replace=False)
-
-
 @pytest.mark.parametrize("kind,bits", [(O.KIND_OT, 64), (O.KIND_OD, 64)])
 def test_headline_keys_and_fused_call(rr, city, kind, bits):
     w, scene, bvh = city
@@ -71,8 +66,9 @@ def test_headline_keys_and_fused_call(rr, city, kind, bits):
     assert int(cnt.cpu().numpy()[0]) == n
     assert np.array_equal(perm.cpu().numpy().view(np.uint32), want_perm)
     h = rr.hits_to_numpy(hits)
-    s = sample(n, bits + kind)
-    assert h[s].tobytes() == bvh.trace(w.rays[want_perm[s]]).tobytes()
+    # every hit, in key order, against the oracle's trace of the sorted rays
+    sorted_rays = np.ascontiguousarray(w.rays[want_perm])
+    assert_hits_match(h, bvh.trace(sorted_rays), sorted_rays, w.tris, f"headline kind {kind}")
     # hits scattered back equal the unsorted trace, every ray
     back, _, _ = rr.rr_reorder_and_trace(scene, rays, p, flags=rr.RR_HITS_ORIGINAL_ORDER)
     plain = rr.hits_to_numpy(rr.rr_trace(scene, rays))
@@ -94,9 +90,9 @@ def test_bounce3_compacted(rr, city):
     order = np.lexsort((live, k))
     want_perm = live[order].astype(np.uint32)
     assert np.array_equal(perm.cpu().numpy().view(np.uint32)[:c], want_perm)
-    h = rr.hits_to_numpy(hits)
-    s = sample(c, 3)
-    assert h[s].tobytes() == bvh.trace(w3.rays[want_perm[s]]).tobytes()
+    h = rr.hits_to_numpy(hits)[:c]
+    sorted_rays = np.ascontiguousarray(w3.rays[want_perm])
+    assert_hits_match(h, bvh.trace(sorted_rays), sorted_rays, w.tris, "bounce-3")
 
 
 def test_batch_64_wavefronts(rr, city):
@@ -112,25 +108,26 @@ def test_batch_64_wavefronts(rr, city):
     with_perm = [rr.segment(r, h, key, perm=q) for (r, h), q in zip(keep, perms)]
     rays_np = [r.cpu().numpy() for r, _ in keep]
     want = []
+    want_hits = []
     for rn in rays_np:
         _, wp = O.sort_pairs(O.keys(rn, O.KIND_OT, 64, lo, hi, 0.25))
         want.append(wp)
+        want_hits.append(bvh.trace(np.ascontiguousarray(rn[wp])))
     for shape in (None, bench.BATCH_PROFILE_SHAPE):
         with rr.Batch(scene, max_rays=total, max_segments=len(segs), config=shape) as b:
             b.run(with_perm, flags=0)
             torch.cuda.synchronize()
         for j, ((r, h), q) in enumerate(zip(keep, perms)):
             assert np.array_equal(q.cpu().numpy().view(np.uint32), want[j]), (shape, j)
-            s = sample(r.shape[0], 100 + j)[:256]
             got = rr.hits_to_numpy(h)
-            assert got[s].tobytes() == bvh.trace(rays_np[j][want[j][s]]).tobytes(), (shape, j)
+            assert_hits_match(got, want_hits[j], rays_np[j][want[j]], w.tris, f"{shape} segment {j}")
 
 
 def test_served_4m_city(rr):
     """The serving configuration of the bench (~4M-triangle city, requests
     of 16K to 4M rays with mixed key methods, two slots, 32 GB budget): every
-    served hit equals the unsorted trace of its request, and a sample of 512
-    per request equals the oracle's trace."""
+    served hit equals the unsorted trace of its request and the oracle's
+    trace of the request."""
     c = W.city(5, 200, 200, 3_520_000)
     r = W.camera_rays(5, 3840, 2160, (100.0, 120.0, 100.0))
     r, alive = W.bounce(c, 5, 300, r, np.ones(r.shape[0], np.uint8))
@@ -158,5 +155,4 @@ def test_served_4m_city(rr):
         for j, (rn, rd, h, _) in enumerate(reqs):
             got = rr.hits_to_numpy(h)
             assert got.tobytes() == rr.hits_to_numpy(rr.rr_trace(scene, rd)).tobytes(), j
-            s = sample(rn.shape[0], 500 + j)[:512]
-            assert got[s].tobytes() == bvh.trace(rn[s]).tobytes(), j
+            assert_hits_match(got, bvh.trace(rn), rn, c.tris, f"request {j}")

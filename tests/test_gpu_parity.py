@@ -11,6 +11,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from hitcheck import assert_hits_match
 
 pytestmark = pytest.mark.gpu
 
@@ -41,23 +42,6 @@ def keys_np(t, bits):
 
 def idx_np(t):
     return t.cpu().numpy().view(np.uint32)
-
-
-def assert_hits_match(gpu, ref, rays, tris, what=""):
-    """prim exact except near-ties; t, u, v bit-exact when prim matches."""
-    same = gpu["prim"] == ref["prim"]
-    bad = np.nonzero(~same)[0]
-    for i in bad[:1000]:
-        gp, op = int(gpu["prim"][i]), int(ref["prim"][i])
-        assert gp >= 0 and op >= 0, f"{what}: hit/miss mismatch at ray {i}: gpu {gp} oracle {op}"
-        ok, t, _, _ = O.mt(rays[i], tris[gp])
-        assert ok and abs(t - ref["t"][i]) <= 1e-5 * abs(ref["t"][i]), f"{what}: ray {i}"
-        assert abs(gpu["t"][i] - ref["t"][i]) <= 1e-5 * abs(ref["t"][i]), f"{what}: ray {i}"
-    assert len(bad) <= max(2, len(ref) // 10000), f"{what}: {len(bad)} near-tie differences"
-    m = same
-    assert np.array_equal(gpu["t"][m].view(np.uint32), ref["t"][m].view(np.uint32)), what
-    assert np.array_equal(gpu["u"][m].view(np.uint32), ref["u"][m].view(np.uint32)), what
-    assert np.array_equal(gpu["v"][m].view(np.uint32), ref["v"][m].view(np.uint32)), what
 
 
 # ------------------------------------------------------------------- keys
@@ -354,6 +338,62 @@ def test_trace_degenerate_geometry(rr, scale):
             p = rr.key_params(O.KIND_OT, 64, lo, hi, 0.25)
             back, _, _ = rr.rr_reorder_and_trace(sc, rd, p, flags=rr.RR_HITS_ORIGINAL_ORDER)
             assert rr.hits_to_numpy(back).tobytes() == ref.tobytes(), (scale, builder)
+
+
+def stacked_scene(n, n_rays, seed):
+    """n near-parallel triangles stacked in z over one unit footprint (ids in
+    random order), and rays that cross the stack: from below, from above,
+    and from inside it in random directions.  Every box of a descent is hit,
+    so a traversal pushes three entries per level of the 4-wide tree."""
+    rng = np.random.default_rng(seed)
+    z = (np.arange(n) + rng.uniform(0.1, 0.9, n)) / n
+    a = rng.uniform(-0.01, 0.01, (n, 2))
+    T = np.zeros((n, 9), np.float32)
+    T[:, 0], T[:, 1], T[:, 2] = a[:, 0], a[:, 1], z
+    T[:, 3], T[:, 4], T[:, 5] = a[:, 0] + 1.0, a[:, 1], z
+    T[:, 6], T[:, 7], T[:, 8] = a[:, 0], a[:, 1] + 1.0, z
+    T = np.ascontiguousarray(T[rng.permutation(n)])
+    m = n_rays // 3
+    xy = rng.uniform(0.02, 0.45, (n_rays, 2))
+    o = np.zeros((n_rays, 3))
+    d = np.zeros((n_rays, 3))
+    o[:, :2] = xy
+    o[:m, 2] = -0.5
+    d[:m] = np.c_[rng.normal(0, 0.05, (m, 2)), np.ones(m)]
+    o[m:2 * m, 2] = 1.5
+    d[m:2 * m] = np.c_[rng.normal(0, 0.05, (m, 2)), -np.ones(m)]
+    o[2 * m:, 2] = rng.uniform(0.0, 1.0, n_rays - 2 * m)
+    d[2 * m:] = rng.normal(size=(n_rays - 2 * m, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rays = np.zeros((n_rays, 8), np.float32)
+    rays[:, 0:3], rays[:, 4:7] = o, d
+    rays[:, 3], rays[:, 7] = 0.0, np.inf
+    return T, rays
+
+
+@pytest.mark.parametrize("builder", [0, 1, 1 | 2])
+def test_trace_deep_stack_spills_to_scratch(rr, builder):
+    """A scene whose traversals need more stack entries than the 16 held in
+    LDS: the profiling counters show the scratch part in use, and every hit
+    equals brute force (with both builders and full-precision nodes)."""
+    T, rays = stacked_scene(1 << 17, 3072, 61)
+    ref = O.brute_force(T, rays)
+    assert (ref["prim"] >= 0).mean() > 0.5
+    with rr.Scene(T, builder=builder) as sc:
+        rd = to_dev(rays)
+        prof = rr.rr_trace_profile(sc, rd)
+        assert prof["max_stack"] > 16 and prof["spill_pushes"] > 0, prof
+        h = rr.hits_to_numpy(rr.rr_trace(sc, rd))
+        assert_hits_match(h, ref, rays, T, f"stack builder {builder}")
+        # the profiling variant returns the same hits
+        hp = torch.empty((rays.shape[0], 4), dtype=torch.float32, device=DEV)
+        rr.rr_trace_profile(sc, rd, hits=hp)
+        assert rr.hits_to_numpy(hp).tobytes() == h.tobytes()
+        # reordered (and traced in key order) the hits are unchanged
+        lo, hi = sc.bounds()
+        back, _, _ = rr.rr_reorder_and_trace(sc, rd, rr.key_params(O.KIND_OT, 64, lo, hi, 0.25),
+                                             flags=rr.RR_HITS_ORIGINAL_ORDER)
+        assert rr.hits_to_numpy(back).tobytes() == h.tobytes()
 
 
 # ---------------------------------------------------------- fused pipeline
