@@ -218,9 +218,13 @@ rr_status rr_coherence_m64(const rr_ray* rays, const rr_hit* hits, int64_t n, co
                            double* group_out, double* mean_out, void* stream);
 
 /* ------------------------------------------------------------------- sort
- * Section 3.2: stable ascending LSD radix sort of (key, index) pairs, in
- * place.  The result is unique: the lexicographic order of (key, index)
- * when the input indices ascend.  n_max is the capacity; when count_dev
+ * Section 3.2: stable ascending radix sort of (key, index) pairs, in place.
+ * The result is unique: the lexicographic order of (key, index) when the
+ * input indices ascend (in general: by key, equal keys in input position
+ * order).  For 64-bit keys below 2^27 pairs rr_sort runs a most-significant-
+ * digit sort (two stable scatter passes on the two highest 8-bit digits in
+ * which the keys differ, then every bucket of equal top digits sorted on its
+ * other digits in LDS); otherwise an LSD sort with 8-bit digits.  n_max is the capacity; when count_dev
  * (device uint32) is given, only its first *count_dev pairs are sorted
  * (count_dev must not exceed n_max).  workspace (device, >= the size
  * reported by rr_sort_workspace_size, 256-byte aligned) is scratch that the
@@ -231,9 +235,10 @@ rr_status rr_coherence_m64(const rr_ray* rays, const rr_hit* hits, int64_t n, co
 rr_status rr_sort_workspace_size(int64_t n_max, uint32_t key_bits, size_t* bytes);
 rr_status rr_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                   void* workspace, size_t ws_bytes, void* stream);
-/* Same, with an explicit radix digit width (4 or 8 bits) and keys per
- * thread (tile size); every choice gives the identical result.  rr_sort uses
- * 8-bit digits and 8 keys per thread, 16 from 2^24 keys (n_max) on. */
+/* The LSD sort with an explicit radix digit width (4 or 8 bits) and keys
+ * per thread (tile size); every choice gives the identical result, that of
+ * rr_sort.  rr_sort's LSD sort and scatter passes use 8-bit digits and 8 keys
+ * per thread, 16 from 2^24 keys (n_max) on. */
 rr_status rr_sort_ex(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                      uint32_t digit_bits, uint32_t keys_per_thread, void* workspace, size_t ws_bytes,
                      void* stream);

@@ -245,8 +245,13 @@ rr_status rr_sort_ex(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* c
 
 rr_status rr_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                   void* workspace, size_t ws_bytes, void* stream) {
-  return rr_sort_ex(keys, idx, n_max, count_dev, key_bits, 8, sort_default_kpt(n_max), workspace, ws_bytes,
-                    stream);
+  if (!valid_n(n_max) || (key_bits != 32 && key_bits != 64)) return RR_ERR_INVALID_ARGUMENT;
+  if (n_max == 0) return RR_OK;
+  if (!is_device_ptr(keys) || !is_device_ptr(idx) || !is_device_ptr(workspace)) return RR_ERR_INVALID_ARGUMENT;
+  if (!aligned(keys, key_bits / 8) || !aligned(idx, 4) || !aligned(workspace, 256)) return RR_ERR_INVALID_ARGUMENT;
+  if (count_dev && !is_device_ptr(count_dev)) return RR_ERR_INVALID_ARGUMENT;
+  if (ws_bytes < sort_workspace_bytes_any(n_max, key_bits)) return RR_ERR_WORKSPACE_TOO_SMALL;
+  return launch_sort_auto(keys, idx, n_max, count_dev, key_bits, workspace, ws_bytes, S(stream));
 }
 
 rr_status rr_local_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
@@ -424,7 +429,7 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
                                   st)) != RR_OK)
         return r;
       gathered = true;
-    } else if ((r = launch_sort(keys, idx, n, cnt, kb, 8, sort_default_kpt(n), w + L.sortws, L.sort_bytes, st)) != RR_OK) {
+    } else if ((r = launch_sort_auto(keys, idx, n, cnt, kb, w + L.sortws, L.sort_bytes, st)) != RR_OK) {
       return r;
     }
   } else {

@@ -124,6 +124,27 @@ __global__ void k_seg_init(const SortHdr* hdr, uint32_t* __restrict__ hist, uint
     for (uint32_t i = threadIdx.x; i < n_counters; i += blockDim.x) counters[i] = 0;
 }
 
+// The single segment of the most-significant-digit sort (n = min(*count_dev,
+// n_max) keys): clears the digit histograms and the (dh, dl) bucket sizes,
+// and empties the second pass's header, which its first pass fills when
+// there are keys.
+__global__ void k_msd_setup(const uint32_t* count_dev, uint32_t n_max, uint32_t tile, SortHdr* hdr, SortSeg* segs,
+                            uint32_t* __restrict__ hist, uint32_t hist_words, uint32_t* __restrict__ hist2,
+                            uint32_t hist2_words, SortHdr* hdr2, MsdPlan* plan) {
+  const uint32_t stride = gridDim.x * blockDim.x, gid = blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint32_t i = gid; i < hist_words; i += stride) hist[i] = 0;
+  for (uint32_t i = gid; i < hist2_words; i += stride) hist2[i] = 0;
+  if (gid == 0) {
+    uint32_t n = n_max;
+    if (count_dev) n = min(*count_dev, n_max);
+    const uint32_t tiles = (n + tile - 1) / tile;
+    segs[0] = SortSeg{0u, n, 0u, tiles};
+    *hdr = SortHdr{1u, tiles, n, 0u};
+    *hdr2 = SortHdr{0u, 0u, 0u, 0u};
+    *plan = MsdPlan{1u, 0u, 0u, 0u};
+  }
+}
+
 // Digit histograms of every pass per segment.  Blocks take contiguous runs
 // of kHistUnit-key units (a unit never straddles a segment), load a unit's
 // keys before counting them, and flush their LDS counts when the segment
@@ -167,6 +188,10 @@ __device__ __forceinline__ void clear_lookback(uint32_t* __restrict__ status, ui
   }
 }
 
+// With a plan (the second pass of the most-significant-digit sort) only
+// digit plan->dl is counted, as the histogram of pass 0.  The look-back
+// words of clear_passes passes are cleared for the segments' tiles plus
+// extra_tiles, and their groups plus extra_groups.
 template <typename K, int DB, int KPT>
 __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__ keys, const SortHdr* hdr,
                                                            const SortSeg* __restrict__ segs, uint32_t passes,
@@ -174,7 +199,9 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
                                                            uint32_t* __restrict__ status,
                                                            uint32_t status_pass_stride,
                                                            uint32_t* __restrict__ gstatus,
-                                                           uint32_t gstatus_pass_stride) {
+                                                           uint32_t gstatus_pass_stride, const MsdPlan* plan,
+                                                           uint32_t clear_passes, uint32_t extra_tiles,
+                                                           uint32_t extra_groups) {
   constexpr uint32_t R = 1u << DB;
   constexpr uint32_t kTile = kSortThreads * KPT;
   constexpr uint32_t kUnitsPerTile = kTile >= kHistUnit ? kTile / kHistUnit : 1u;
@@ -188,6 +215,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
   const uint32_t U = T * kUnitsPerTile;
   const uint32_t words = passes * R;
   const uint32_t copy = blockIdx.x % copies;
+  const uint32_t shift0 = plan ? plan->dl * DB : 0u;  // digit of pass 0
   uint32_t* const lane_h = s_h + (threadIdx.x % kHistLaneCopies) * kStride;
   for (uint32_t i = threadIdx.x; i < kHistLaneCopies * kStride; i += kSortThreads) s_h[i] = 0;
   __syncthreads();
@@ -217,13 +245,15 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_hist(const K* __restrict__
     for (uint32_t q = 0; q < kPer; ++q) {
       if (first + q * kSortThreads + threadIdx.x >= last) continue;
       for (uint32_t p = 0; p < passes; ++p)
-        atomicAdd(&lane_h[p * R + ((uint32_t)(k[q] >> (p * DB)) & (R - 1))], 1u);
+        atomicAdd(&lane_h[p * R + ((uint32_t)(k[q] >> (shift0 + p * DB)) & (R - 1))], 1u);
     }
   }
   __syncthreads();
   if (u0 < u1) flush_lane_hist(s_h, kStride, words, hist + ((size_t)cur * copies + copy) * words);
-  // clear the look-back words of the tiles and groups this sort will use
-  clear_lookback(status, status_pass_stride, T, gstatus, gstatus_pass_stride, T / kGroup + nseg, passes, R);
+  // clear the look-back words of the tiles and groups the passes will use
+  if (clear_passes)
+    clear_lookback(status, status_pass_stride, T + extra_tiles, gstatus, gstatus_pass_stride,
+                   (T + extra_tiles) / kGroup + nseg + extra_groups, clear_passes, R);
 }
 
 // The keys of a dense single-segment sort computed and counted in one pass
@@ -242,7 +272,8 @@ __global__ __launch_bounds__(kSortThreads) void k_keys_hist(const float4* __rest
                                                             uint32_t* __restrict__ status,
                                                             uint32_t status_pass_stride, uint32_t status_tiles,
                                                             uint32_t* __restrict__ gstatus,
-                                                            uint32_t gstatus_pass_stride, uint32_t status_groups) {
+                                                            uint32_t gstatus_pass_stride, uint32_t status_groups,
+                                                            uint32_t clear_passes) {
   constexpr int DB = 8;
   constexpr uint32_t R = 1u << DB;
   constexpr uint32_t kPer = kHistUnit / kSortThreads;
@@ -274,7 +305,8 @@ __global__ __launch_bounds__(kSortThreads) void k_keys_hist(const float4* __rest
   }
   __syncthreads();
   if (u0 < u1) flush_lane_hist(s_h, kStride, words, hist + (size_t)copy * words);
-  clear_lookback(status, status_pass_stride, status_tiles, gstatus, gstatus_pass_stride, status_groups, passes, R);
+  clear_lookback(status, status_pass_stride, status_tiles, gstatus, gstatus_pass_stride, status_groups, clear_passes,
+                 R);
 }
 
 template <typename K, int DB, int KPT>
@@ -288,6 +320,25 @@ struct PassSmem {
   uint32_t base[R];
   uint32_t scan[kSortWaves];
   uint32_t ticket;  // next tile, when tiles come from a counter
+  uint32_t nonuni;  // digits in which the keys differ (the first pass of the MSD sort)
+};
+
+// The two scatter passes of the most-significant-digit sort; mode 0 is a
+// pass of the LSD sort.  Mode 1, the first pass of a single-segment sort:
+// every block picks the digits itself from the histograms and the first key
+// (digit d is the same in every key exactly when the first key's digit-d
+// value counts all keys): dh is the highest digit that differs, dl the next
+// one below it (another digit when none below differs); the pass scatters by
+// dh, and the block holding tile 0 writes the plan and the 256 segments of
+// the second pass, one per value of dh.  Mode 2, the second pass: scatters
+// each of those segments by digit dl and records where every (dh, dl)
+// bucket starts.
+struct MsdArgs {
+  uint32_t mode;
+  MsdPlan* plan;
+  SortHdr* hdr2;
+  SortSeg* segs2;
+  uint32_t* bstart;
 };
 
 __device__ __forceinline__ uint32_t load_status(const uint32_t* p) {
@@ -422,13 +473,14 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
                                                            const uint32_t* __restrict__ idx_in,
                                                            K* __restrict__ keys_out, uint32_t* __restrict__ idx_out,
                                                            const SortHdr* hdr, const SortSeg* __restrict__ segs,
-                                                           uint32_t shift, uint32_t passes, uint32_t pass,
+                                                           uint32_t shift_in, uint32_t passes, uint32_t pass_in,
                                                            uint32_t copies, const uint32_t* __restrict__ hist,
                                                            uint32_t* __restrict__ status,
                                                            uint32_t* __restrict__ gstatus,
                                                            uint32_t* tile_counter,
                                                            const float4* __restrict__ gather_in,
-                                                           float4* __restrict__ gather_out, uint32_t gather_n) {
+                                                           float4* __restrict__ gather_out, uint32_t gather_n,
+                                                           MsdArgs msd) {
   using S = PassSmem<K, DB, KPT>;
   constexpr uint32_t R = S::R;
   constexpr uint32_t kTile = S::kTile;
@@ -439,6 +491,28 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
   uint32_t cur = 0xFFFFFFFFu;  // segment whose digit bases are in sm.base
 
   for (uint32_t i = tid; i < kSortWaves * R; i += kSortThreads) (&sm.wave_hist[0][0])[i] = 0;
+
+  uint32_t shift = shift_in, pass = pass_in, dh = 0, dl = 0;
+  if (msd.mode == 1) {
+    if (tid == 0) sm.nonuni = 0;
+    __syncthreads();
+    const uint32_t n_all = hdr->total_keys;
+    if (tid < passes && n_all > 0) {
+      const uint32_t dg = (uint32_t)(keys_in[seg0.off] >> (tid * DB)) & (R - 1);
+      uint32_t c = 0;
+      for (uint32_t cc = 0; cc < copies; ++cc) c += hist[((size_t)cc * passes + tid) * R + dg];
+      if (c != n_all) atomicOr(&sm.nonuni, 1u << tid);
+    }
+    __syncthreads();
+    const uint32_t m = sm.nonuni;
+    dh = m ? 31u - (uint32_t)__builtin_clz(m) : passes - 1;
+    const uint32_t below = m & ((1u << dh) - 1u);
+    dl = below ? 31u - (uint32_t)__builtin_clz(below) : (dh > 0 ? dh - 1 : 1u);
+    shift = dh * DB;
+    pass = dh;
+  } else if (msd.mode == 2) {
+    shift = msd.plan->dl * DB;
+  }
 
   // Keys and indices of a tile, loaded wave-striped: wave w owns KPT
   // consecutive groups of 64.  The next tile's loads are issued before the
@@ -507,6 +581,20 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
         for (uint32_t c = 0; c < copies; ++c) h += hist[(((size_t)s * copies + c) * passes + pass) * R + tid];
       const uint32_t ex = block_scan(h, sm.scan, &total);
       if (tid < R) sm.base[tid] = sg.off + ex;
+      if (msd.mode == 2 && lt == 0 && tid < R) msd.bstart[(size_t)s * R + tid] = sg.off + ex;
+      if (msd.mode == 1) {
+        // the segments of the second pass: one per value of digit dh
+        const uint32_t nt = tid < R ? (h + kTile - 1) / kTile : 0u;
+        uint32_t ttot;
+        const uint32_t tex = block_scan(nt, sm.scan, &ttot);
+        if (tile == 0) {
+          if (tid < R) msd.segs2[tid] = SortSeg{sg.off + ex, h, tex, nt};
+          if (tid == 0) {
+            *msd.hdr2 = SortHdr{R, ttot, total, 0u};
+            *msd.plan = MsdPlan{dh, dl, total, 0u};
+          }
+        }
+      }
       cur = s;
     }
 
@@ -602,6 +690,351 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// The last kernel of the most-significant-digit sort.  After its two scatter
+// passes the keys are grouped into buckets of equal (dh, dl) digits, in
+// bucket order, each bucket in input order.  Block b takes the buckets that
+// start in its window of kLocWindow positions and collects consecutive ones
+// into batches of at most kLocCap keys (where a batch ends is found from the
+// keys themselves: a bucket starts where the bucket number changes, and its
+// size is known).  A batch is sorted in LDS by stable counting passes over
+// the other digits in which its keys differ, least significant first, and
+// then over the bucket number relative to the batch's first bucket, which
+// restores the bucket order.  A bucket larger than a batch is sorted by its
+// block alone with the same stable passes run chunk by chunk through global
+// memory, the alternate buffers taking every other pass.
+constexpr int kLocThreads = 1024;
+constexpr int kLocWaves = kLocThreads / kWave;
+constexpr int kLocKpt = 8;
+constexpr uint32_t kLocCap = kLocThreads * kLocKpt;  // keys of a batch
+constexpr uint32_t kLocWindow = kLocCap;             // positions whose buckets a block takes
+
+template <typename K>
+struct LocSmem {
+  K keys[kLocCap];
+  uint32_t idx[kLocCap];
+  uint32_t wave_hist[kLocWaves][256];
+  uint32_t base[256];           // exclusive digit offsets of the last ranking
+  uint32_t cnt[256];            // digit counts of the last ranking
+  uint32_t run[256];            // large bucket: next output position per digit
+  uint32_t fh[sizeof(K)][256];  // large bucket: its digit histograms
+  uint32_t scan[kLocWaves];
+  uint32_t red[4];
+};
+
+// Exclusive scan of one value per thread over a block of NW waves.
+template <int NW>
+__device__ __forceinline__ uint32_t block_scan_n(uint32_t v, uint32_t* s, uint32_t* total) {
+  const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, kWave);
+    if (lane >= (uint32_t)off) x += y;
+  }
+  if (lane == kWave - 1) s[wave] = x;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const uint32_t t = s[w];
+    pre += (uint32_t)w < wave ? t : 0u;
+    tot += t;
+  }
+  *total = tot;
+  __syncthreads();
+  return pre + x - v;
+}
+
+// Position of element j of this thread in a batch: waves own kLocKpt
+// consecutive groups of 64.
+__device__ __forceinline__ uint32_t loc_pos(int j) {
+  return ((threadIdx.x / kWave) * kLocKpt + (uint32_t)j) * kWave + (threadIdx.x & (kWave - 1));
+}
+
+// Stable ranking by the 8-bit digits dg of the batch positions below nb:
+// pos[j] receives the place of element j in the order by digit that keeps
+// equal digits in position order.  Leaves the digit counts in sm.cnt and
+// their exclusive offsets in sm.base; sm.wave_hist is zero on entry and on
+// return.
+template <typename K>
+__device__ void loc_rank(LocSmem<K>& sm, const uint32_t (&dg)[kLocKpt], uint32_t nb, uint32_t (&pos)[kLocKpt]) {
+  const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  uint32_t rank[kLocKpt], old[kLocKpt];
+#pragma unroll
+  for (int j = 0; j < kLocKpt; ++j) {
+    const bool ok = loc_pos(j) < nb;
+    const uint64_t peers = match_digit<8>(dg[j], __ballot(ok));
+    const uint32_t leader = ok ? (uint32_t)__builtin_ctzll(peers) : lane;
+    rank[j] = lanes_below(peers) | (leader << 16);
+    old[j] = 0;
+    if (ok && lane == leader) old[j] = atomicAdd(&sm.wave_hist[wave][dg[j]], (uint32_t)__popcll(peers));
+  }
+#pragma unroll
+  for (int j = 0; j < kLocKpt; ++j) rank[j] = (rank[j] & 0xFFFFu) + __shfl(old[j], (int)(rank[j] >> 16), kWave);
+  __syncthreads();
+  // per digit: the waves' exclusive prefixes in place, then the digit offset
+  uint32_t c = 0;
+  if (tid < 256) {
+#pragma unroll
+    for (int w = 0; w < kLocWaves; ++w) {
+      const uint32_t t = sm.wave_hist[w][tid];
+      sm.wave_hist[w][tid] = c;
+      c += t;
+    }
+  }
+  uint32_t total;
+  const uint32_t ex = block_scan_n<kLocWaves>(tid < 256 ? c : 0u, sm.scan, &total);
+  if (tid < 256) {
+    sm.base[tid] = ex;
+    sm.cnt[tid] = c;
+#pragma unroll
+    for (int w = 0; w < kLocWaves; ++w) sm.wave_hist[w][tid] += ex;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kLocKpt; ++j)
+    if (loc_pos(j) < nb) pos[j] = sm.wave_hist[wave][dg[j]] + rank[j];
+  __syncthreads();
+  for (uint32_t i = tid; i < kLocWaves * 256; i += kLocThreads) (&sm.wave_hist[0][0])[i] = 0;
+  __syncthreads();
+}
+
+// One stable pass of a batch in LDS: the elements held in registers move to
+// their places in the order by dg, and each thread then holds the elements
+// of its positions again.
+template <typename K>
+__device__ void loc_pass(LocSmem<K>& sm, K (&k)[kLocKpt], uint32_t (&v)[kLocKpt], const uint32_t (&dg)[kLocKpt],
+                         uint32_t nb) {
+  uint32_t pos[kLocKpt];
+  loc_rank(sm, dg, nb, pos);
+#pragma unroll
+  for (int j = 0; j < kLocKpt; ++j) {
+    if (loc_pos(j) < nb) {
+      sm.keys[pos[j]] = k[j];
+      sm.idx[pos[j]] = v[j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kLocKpt; ++j) {
+    const uint32_t p = loc_pos(j);
+    if (p < nb) {
+      k[j] = sm.keys[p];
+      v[j] = sm.idx[p];
+    }
+  }
+  __syncthreads();
+}
+
+// The ray gather of the fused call for sorted positions [i0, i1).
+__device__ __forceinline__ void loc_gather_one(const float4* __restrict__ in, float4* __restrict__ out, uint32_t n_in,
+                                               uint32_t at, uint32_t v) {
+  const float nan = __int_as_float(0x7fc00000);
+  float4 a = make_float4(nan, nan, nan, nan), b = a;
+  if (v < n_in) {
+    a = in[2 * (size_t)v];
+    b = in[2 * (size_t)v + 1];
+  }
+  out[2 * (size_t)at] = a;
+  out[2 * (size_t)at + 1] = b;
+}
+
+// A bucket of m > kLocCap keys at [r0, r0 + m), sorted by this block alone:
+// the histograms of its digits (all but dh and dl, which its keys share),
+// then one stable pass per digit that differs, least significant first,
+// chunk by chunk in position order, between the buffers and the alternate
+// buffers at the same positions.
+template <typename K>
+__device__ void loc_big(LocSmem<K>& sm, K* __restrict__ keys, uint32_t* __restrict__ idx, K* __restrict__ kalt,
+                        uint32_t* __restrict__ ialt, uint32_t r0, uint32_t m, uint32_t dh, uint32_t dl,
+                        const float4* __restrict__ gather_in, float4* __restrict__ gather_out, uint32_t gather_n) {
+  constexpr uint32_t P = sizeof(K);
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < P * 256; i += kLocThreads) (&sm.fh[0][0])[i] = 0;
+  __syncthreads();
+  const K kfirst = keys[r0];
+  for (uint32_t i = r0 + tid; i < r0 + m; i += kLocThreads) {
+    const K x = keys[i];
+    for (uint32_t d = 0; d < P; ++d)
+      if (d != dh && d != dl) atomicAdd(&sm.fh[d][(uint32_t)(x >> (8 * d)) & 255u], 1u);
+  }
+  __syncthreads();
+  K* sk = keys;
+  uint32_t* si = idx;
+  K* dk = kalt;
+  uint32_t* di = ialt;
+#pragma unroll 1
+  for (uint32_t d = 0; d < P; ++d) {
+    if (d == dh || d == dl) continue;
+    if (sm.fh[d][(uint32_t)(kfirst >> (8 * d)) & 255u] == m) continue;  // the same in every key
+    uint32_t tot;
+    const uint32_t ex = block_scan_n<kLocWaves>(tid < 256 ? sm.fh[d][tid] : 0u, sm.scan, &tot);
+    if (tid < 256) sm.run[tid] = r0 + ex;
+    __syncthreads();
+    for (uint32_t c0 = r0; c0 < r0 + m; c0 += kLocCap) {
+      const uint32_t nb = min(kLocCap, r0 + m - c0);
+      K k[kLocKpt];
+      uint32_t v[kLocKpt], dg[kLocKpt], pos[kLocKpt];
+#pragma unroll
+      for (int j = 0; j < kLocKpt; ++j) {
+        const uint32_t p = loc_pos(j);
+        k[j] = p < nb ? sk[c0 + p] : (K)0;
+        v[j] = p < nb ? si[c0 + p] : 0u;
+        dg[j] = (uint32_t)(k[j] >> (8 * d)) & 255u;
+      }
+      loc_rank(sm, dg, nb, pos);
+#pragma unroll
+      for (int j = 0; j < kLocKpt; ++j) {
+        if (loc_pos(j) < nb) {
+          const uint32_t out = sm.run[dg[j]] + (pos[j] - sm.base[dg[j]]);
+          dk[out] = k[j];
+          di[out] = v[j];
+        }
+      }
+      __syncthreads();
+      if (tid < 256) sm.run[tid] += sm.cnt[tid];
+      __syncthreads();
+    }
+    K* tk = sk; sk = dk; dk = tk;
+    uint32_t* ti = si; si = di; di = ti;
+  }
+  if (sk != keys) {
+    for (uint32_t i = r0 + tid; i < r0 + m; i += kLocThreads) {
+      if (!gather_out) keys[i] = sk[i];
+      idx[i] = si[i];
+    }
+  }
+  __syncthreads();
+  if (gather_out)
+    for (uint32_t i = r0 + tid; i < r0 + m; i += kLocThreads) loc_gather_one(gather_in, gather_out, gather_n, i, idx[i]);
+  __syncthreads();
+}
+
+template <typename K>
+__global__ __launch_bounds__(kLocThreads) void k_msd_local(K* __restrict__ keys, uint32_t* __restrict__ idx,
+                                                           K* __restrict__ kalt, uint32_t* __restrict__ ialt,
+                                                           const SortHdr* hdr, const MsdPlan* plan,
+                                                           const uint32_t* __restrict__ bstart,
+                                                           const uint32_t* __restrict__ bcount,
+                                                           const float4* __restrict__ gather_in,
+                                                           float4* __restrict__ gather_out, uint32_t gather_n) {
+  __shared__ LocSmem<K> sm;
+  constexpr uint32_t P = sizeof(K);
+  const uint32_t n = hdr->total_keys;
+  const uint32_t wb = blockIdx.x * kLocWindow;
+  if (wb >= n) return;
+  const uint32_t we = min(n, wb + kLocWindow);
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < kLocWaves * 256; i += kLocThreads) (&sm.wave_hist[0][0])[i] = 0;
+  __syncthreads();
+  const uint32_t dh = plan->dh, dl = plan->dl;
+  const uint32_t sh = dh * 8, sl = dl * 8;
+  auto bucket = [&](K x) -> uint32_t { return (((uint32_t)(x >> sh) & 255u) << 8) | ((uint32_t)(x >> sl) & 255u); };
+  // the first bucket that starts in the window
+  uint32_t p0;
+  {
+    const uint32_t j = bucket(keys[wb]);
+    const uint32_t st = bstart[j];
+    p0 = st == wb ? wb : st + bcount[j];
+  }
+  while (p0 < we) {  // block-uniform
+    const uint32_t lim = min(kLocCap, n - p0);
+    K k[kLocKpt];
+    uint32_t v[kLocKpt];
+#pragma unroll
+    for (int j = 0; j < kLocKpt; ++j) {
+      const uint32_t p = loc_pos(j);
+      k[j] = p < lim ? keys[p0 + p] : (K)0;
+      v[j] = p < lim ? idx[p0 + p] : 0u;
+    }
+    if (tid < 4) sm.red[tid] = 0;
+#pragma unroll
+    for (int j = 0; j < kLocKpt; ++j) {
+      const uint32_t p = loc_pos(j);
+      if (p < lim) sm.keys[p] = k[j];
+    }
+    __syncthreads();
+    const K kfirst = sm.keys[0];
+    const uint32_t b0 = bucket(kfirst);
+    // the batch ends at the end of the last bucket that starts in the window
+    // and ends within kLocCap keys of p0
+    uint32_t cand = 0;
+#pragma unroll
+    for (int j = 0; j < kLocKpt; ++j) {
+      const uint32_t p = loc_pos(j);
+      if (p < lim && p0 + p < we) {
+        const uint32_t bj = bucket(k[j]);
+        if (p == 0 || bucket(sm.keys[p - 1]) != bj) {
+          const uint32_t e = p + bcount[bj];
+          if (e <= lim && e > cand) cand = e;
+        }
+      }
+    }
+    if (cand) atomicMax(&sm.red[0], cand);
+    __syncthreads();
+    const uint32_t nb = sm.red[0];
+    if (nb == 0) {
+      // the bucket at p0 does not fit a batch (its size is bounded by the
+      // keys that remain, so that every access stays in range)
+      const uint32_t m = max(1u, min(bcount[b0], n - p0));
+      __syncthreads();
+      loc_big(sm, keys, idx, kalt, ialt, p0, m, dh, dl, gather_in, gather_out, gather_n);
+      p0 += m;
+      continue;
+    }
+    // digits in which the batch's keys differ, and its bucket span
+    uint64_t diff = 0;
+    uint32_t rspan = 0;
+#pragma unroll
+    for (int j = 0; j < kLocKpt; ++j) {
+      if (loc_pos(j) < nb) {
+        diff |= (uint64_t)(k[j] ^ kfirst);
+        rspan = max(rspan, bucket(k[j]) - b0);
+      }
+    }
+    if ((uint32_t)diff) atomicOr(&sm.red[1], (uint32_t)diff);
+    if ((uint32_t)(diff >> 32)) atomicOr(&sm.red[2], (uint32_t)(diff >> 32));
+    if (rspan) atomicMax(&sm.red[3], rspan);
+    __syncthreads();
+    const uint64_t dm = (uint64_t)sm.red[1] | ((uint64_t)sm.red[2] << 32);
+    const uint32_t span = sm.red[3];
+    __syncthreads();
+    bool moved = false;
+    uint32_t dg[kLocKpt];
+#pragma unroll 1
+    for (uint32_t d = 0; d < P; ++d) {
+      if (d == dh || d == dl || ((dm >> (8 * d)) & 255u) == 0) continue;
+#pragma unroll
+      for (int j = 0; j < kLocKpt; ++j) dg[j] = (uint32_t)(k[j] >> (8 * d)) & 255u;
+      loc_pass(sm, k, v, dg, nb);
+      moved = true;
+    }
+    // keys equal in every other digit are still in bucket order
+    if (moved && span > 0) {
+#pragma unroll 1
+      for (uint32_t q = 0; q < (span > 255 ? 16u : 8u); q += 8) {
+#pragma unroll
+        for (int j = 0; j < kLocKpt; ++j) dg[j] = ((bucket(k[j]) - b0) >> q) & 255u;
+        loc_pass(sm, k, v, dg, nb);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kLocKpt; ++j) {
+      const uint32_t p = loc_pos(j);
+      if (p < nb) {
+        if (moved) {
+          if (!gather_out) keys[p0 + p] = k[j];
+          idx[p0 + p] = v[j];
+        }
+        if (gather_out) loc_gather_one(gather_in, gather_out, gather_n, p0 + p, v[j]);
+      }
+    }
+    p0 += nb;
+    __syncthreads();  // sm.keys and sm.red are reused by the next batch
+  }
+}
+
 template <typename F>
 uint32_t resident(F kernel, int threads) {
   int dev = 0, cus = 0, per = 0;
@@ -634,12 +1067,13 @@ uint32_t keys_hist_resident() {
 template <typename K>
 void launch_keys_hist(const KeyPlan& P, uint32_t units, const float4* rays, uint32_t n, K* keys, uint32_t* idx,
                       uint32_t passes, uint32_t copies, uint32_t* hist, uint32_t* status, uint32_t status_stride,
-                      uint32_t tiles, uint32_t* gstatus, uint32_t gstatus_stride, uint32_t groups, hipStream_t st) {
+                      uint32_t tiles, uint32_t* gstatus, uint32_t gstatus_stride, uint32_t groups,
+                      uint32_t clear_passes, hipStream_t st) {
 #define RR_KEYS_HIST(F)                                                                                           \
   hipLaunchKernelGGL((k_keys_hist<F, K>), dim3(std::max(1u, std::min(units, std::min(keys_hist_resident<F, K>(), \
                                                                                        1024u)))),              \
                      dim3(kSortThreads), 0, st, rays, n, P, keys, idx, passes, copies, hist, status, status_stride, \
-                     tiles, gstatus, gstatus_stride, groups)
+                     tiles, gstatus, gstatus_stride, groups, clear_passes)
   const int f = key_family(P.kind);
   if (f == 1) RR_KEYS_HIST(1);
   else if (f == 2) RR_KEYS_HIST(2);
@@ -686,12 +1120,13 @@ rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, So
     if constexpr (DB == 8)
       launch_keys_hist<K>(ksrc->plan, (n_max + kHistUnit - 1) / kHistUnit,
                           reinterpret_cast<const float4*>(ksrc->rays), n_max, keys, idx, L.passes, L.hist_copies, hist,
-                          status, L.status_stride, tiles, gstatus, L.gstatus_stride, tiles / kGroup + 1, st);
+                          status, L.status_stride, tiles, gstatus, L.gstatus_stride, tiles / kGroup + 1, L.passes, st);
   } else {
     const uint32_t hist_units = std::max(1u, max_tiles * L.tile / kHistUnit);
     const uint32_t hist_blocks = std::max(1u, std::min(hist_units, std::min(hist_res, 1024u)));
     hipLaunchKernelGGL((k_seg_hist<K, DB, KPT>), dim3(hist_blocks), dim3(kSortThreads), 0, st, keys, hdr, segs,
-                       L.passes, L.hist_copies, hist, status, L.status_stride, gstatus, L.gstatus_stride);
+                       L.passes, L.hist_copies, hist, status, L.status_stride, gstatus, L.gstatus_stride,
+                       (const MsdPlan*)nullptr, L.passes, 0u, 0u);
   }
   // one resident wave of blocks
   const uint32_t pass_blocks = std::max(1u, std::min(max_tiles, pass_res));
@@ -706,7 +1141,7 @@ rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, So
                        g ? nullptr : dst_k, dst_i, hdr, segs, p * DB, L.passes, p, L.hist_copies, hist,
                        status + (size_t)p * L.status_stride, gstatus + (size_t)p * L.gstatus_stride,
                        counted ? counters + p : nullptr, g ? reinterpret_cast<const float4*>(gather_in) : nullptr,
-                       g ? reinterpret_cast<float4*>(gather_out) : nullptr, gather_n);
+                       g ? reinterpret_cast<float4*>(gather_out) : nullptr, gather_n, MsdArgs{});
     std::swap(src_k, dst_k);
     std::swap(src_i, dst_i);
   }
@@ -715,7 +1150,117 @@ rr_status seg_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, So
   return RR_OK;
 }
 
+template <typename K>
+uint32_t msd_local_blocks(uint32_t n_max) {
+  return std::max(1u, (n_max + kLocWindow - 1) / kLocWindow);
+}
+
+// The most-significant-digit sort of one segment of min(*count_dev, n_max)
+// keys (n_max with keys from the rays): histograms of every digit, a stable
+// pass on the highest differing digit dh, histograms of the next one (dl)
+// per dh value, a stable pass on dl within each dh value, then each (dh, dl)
+// bucket sorted on its remaining digits by k_msd_local.  Every step keeps
+// equal keys in input order, so the result is the stable sort.
+template <typename K, int KPT>
+rr_status msd_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, const uint32_t* count_dev,
+                        uint32_t n_max, const rr_ray* gather_in, rr_ray* gather_out, uint32_t gather_n,
+                        hipStream_t st, const KeySource* ksrc = nullptr) {
+  constexpr uint32_t R = 256;
+  K* kalt = reinterpret_cast<K*>(ws + L.keys_alt);
+  uint32_t* ialt = reinterpret_cast<uint32_t*>(ws + L.idx_alt);
+  SortHdr* hdr = reinterpret_cast<SortHdr*>(ws + L.hdr);
+  SortSeg* segs = reinterpret_cast<SortSeg*>(ws + L.segs);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+  MsdPlan* plan = reinterpret_cast<MsdPlan*>(ws + L.plan);
+  SortHdr* hdr2 = reinterpret_cast<SortHdr*>(ws + L.hdr2);
+  SortSeg* segs2 = reinterpret_cast<SortSeg*>(ws + L.segs2);
+  uint32_t* hist2 = reinterpret_cast<uint32_t*>(ws + L.hist2);
+  uint32_t* bstart = reinterpret_cast<uint32_t*>(ws + L.bstart);
+  uint32_t* status2 = reinterpret_cast<uint32_t*>(ws + L.status2);
+  uint32_t* gstatus2 = reinterpret_cast<uint32_t*>(ws + L.gstatus2);
+
+  const uint32_t hist_res = Resident<K, 8, KPT>::hist();
+  const uint32_t pass_res = Resident<K, 8, KPT>::pass();
+  const uint32_t hist_words = L.hist_copies * L.passes * R;
+  hipLaunchKernelGGL(k_msd_setup, dim3(64), dim3(256), 0, st, count_dev, n_max, L.tile, hdr, segs, hist, hist_words,
+                     hist2, R * R, hdr2, plan);
+  // histograms of every digit; the look-back words of both passes are
+  // cleared for up to R more tiles (the second pass's segments each add a
+  // partial tile) and their groups
+  const uint32_t tiles = (n_max + L.tile - 1) / L.tile;
+  if (ksrc) {
+    launch_keys_hist<K>(ksrc->plan, (n_max + kHistUnit - 1) / kHistUnit, reinterpret_cast<const float4*>(ksrc->rays),
+                        n_max, keys, idx, L.passes, L.hist_copies, hist, status2, L.status2_stride, tiles + R,
+                        gstatus2, L.gstatus2_stride, (tiles + R) / kGroup + R + 2, 2u, st);
+  } else {
+    const uint32_t units = std::max(1u, tiles * L.tile / kHistUnit);
+    hipLaunchKernelGGL((k_seg_hist<K, 8, KPT>), dim3(std::max(1u, std::min(units, std::min(hist_res, 1024u)))),
+                       dim3(kSortThreads), 0, st, keys, hdr, segs, L.passes, L.hist_copies, hist, status2,
+                       L.status2_stride, gstatus2, L.gstatus2_stride, (const MsdPlan*)nullptr, 2u, R, R + 1);
+  }
+  // first pass: by dh, into the alternate buffers
+  hipLaunchKernelGGL((k_seg_pass<K, 8, KPT>), dim3(std::max(1u, std::min(L.max_tiles, pass_res))),
+                     dim3(kSortThreads), 0, st, keys, idx, kalt, ialt, hdr, segs, 0u, L.passes, 0u, L.hist_copies, hist,
+                     status2, gstatus2, (uint32_t*)nullptr, (const float4*)nullptr, (float4*)nullptr, 0u,
+                     MsdArgs{1u, plan, hdr2, segs2, bstart});
+  // digit-dl histograms of every dh segment
+  const uint32_t units2 = std::max(1u, (L.max_tiles + R) * L.tile / kHistUnit);
+  hipLaunchKernelGGL((k_seg_hist<K, 8, KPT>), dim3(std::max(1u, std::min(units2, std::min(hist_res, 1024u)))),
+                     dim3(kSortThreads), 0, st, kalt, hdr2, segs2, 1u, 1u, hist2, (uint32_t*)nullptr, 0u,
+                     (uint32_t*)nullptr, 0u, (const MsdPlan*)plan, 0u, 0u, 0u);
+  // second pass: by dl within each dh segment, back into the caller's buffers
+  hipLaunchKernelGGL((k_seg_pass<K, 8, KPT>), dim3(std::max(1u, std::min(L.max_tiles + R, pass_res))),
+                     dim3(kSortThreads), 0, st, kalt, ialt, keys, idx, hdr2, segs2, 0u, 1u, 0u, 1u, hist2,
+                     status2 + L.status2_stride, gstatus2 + L.gstatus2_stride, (uint32_t*)nullptr,
+                     (const float4*)nullptr, (float4*)nullptr, 0u, MsdArgs{2u, plan, nullptr, nullptr, bstart});
+  // every (dh, dl) bucket on its remaining digits (and the ray gather)
+  hipLaunchKernelGGL((k_msd_local<K>), dim3(msd_local_blocks<K>(n_max)), dim3(kLocThreads), 0, st, keys, idx, kalt,
+                     ialt, hdr, plan, bstart, hist2, reinterpret_cast<const float4*>(gather_in),
+                     reinterpret_cast<float4*>(gather_out), gather_n);
+  RR_LAUNCH_CHECK();
+  return RR_OK;
+}
+
 }  // namespace
+
+SegLayout msd_layout(int64_t n_max, uint32_t key_bits, uint32_t kpt) {
+  SegLayout L{};
+  constexpr size_t R = 256;
+  const size_t kb = key_bits / 8;
+  L.msd = true;
+  L.passes = key_bits / 8;
+  L.tile = kSortThreads * kpt;
+  L.max_seg = 1;
+  L.max_tiles = (uint32_t)((n_max + L.tile - 1) / L.tile + 1);
+  L.hist_copies = kHistCopies;
+  size_t off = 0;
+  L.keys_alt = off; off = align_up(off + kb * (size_t)n_max, 256);
+  L.idx_alt = off; off = align_up(off + 4 * (size_t)n_max, 256);
+  L.hdr = off; off = align_up(off + sizeof(SortHdr), 256);
+  L.segs = off; off = align_up(off + sizeof(SortSeg), 256);
+  L.hist = off; off = align_up(off + 4 * (size_t)L.hist_copies * L.passes * R, 256);
+  L.counters = off; off = align_up(off + 4 * (size_t)L.passes, 256);
+  L.plan = off; off = align_up(off + sizeof(MsdPlan), 256);
+  L.hdr2 = off; off = align_up(off + sizeof(SortHdr), 256);
+  L.segs2 = off; off = align_up(off + sizeof(SortSeg) * R, 256);
+  L.hist2 = off; off = align_up(off + 4 * R * R, 256);
+  L.bstart = off; off = align_up(off + 4 * R * R, 256);
+  // the second pass has at most max_tiles + R - 1 tiles; group words of
+  // segment s sit at tile_off / kGroup + s + lt / kGroup
+  const size_t tiles2 = (size_t)L.max_tiles + R;
+  L.status2_stride = (uint32_t)(tiles2 * R);
+  L.status2 = off; off = align_up(off + 4 * 2 * (size_t)L.status2_stride, 256);
+  L.gstatus2_stride = (uint32_t)((tiles2 / kGroup + R + 2) * R);
+  L.gstatus2 = off; off = align_up(off + 4 * 2 * (size_t)L.gstatus2_stride, 256);
+  L.status = L.status2;
+  L.gstatus = L.gstatus2;
+  L.status_stride = L.status2_stride;
+  L.gstatus_stride = L.gstatus2_stride;
+  L.total = off;
+  return L;
+}
+
+bool msd_preferred(int64_t n_max, uint32_t key_bits) { return key_bits == 64 && n_max < (int64_t(1) << 27); }
 
 SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_t db, uint32_t kpt) {
   SegLayout L{};
@@ -760,6 +1305,7 @@ size_t sort_workspace_bytes_any(int64_t n_max, uint32_t key_bits) {
   size_t m = 0;
   for (uint32_t db : {4u, 8u})
     for (uint32_t kpt : {8u, 16u}) m = std::max(m, sort_workspace_bytes(n_max, key_bits, db, kpt));
+  if (msd_preferred(n_max, key_bits)) m = std::max(m, msd_layout(n_max, key_bits, sort_default_kpt(n_max)).total);
   return m;
 }
 
@@ -801,6 +1347,40 @@ rr_status launch_seg_sort(void* keys, uint32_t* idx, const SegLayout& L, void* w
   return RR_ERR_UNSUPPORTED;
 }
 
+namespace {
+
+// The most-significant-digit sort with kpt keys per thread in its scatter
+// passes (keys from the rays when ksrc is given; the ray gather in its last
+// kernel when gather_out is given).
+rr_status launch_msd(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                     uint32_t kpt, void* ws, size_t ws_bytes, const rr_ray* gather_in, rr_ray* gather_out,
+                     uint32_t gather_n, hipStream_t st, const KeySource* ksrc) {
+  const SegLayout L = msd_layout(n_max, key_bits, kpt);
+  if (ws_bytes < L.total) return RR_ERR_WORKSPACE_TOO_SMALL;
+  char* w = reinterpret_cast<char*>(ws);
+#define RR_MSD_CASE(KT, KPTV)                                                                                       \
+  if (sizeof(KT) * 8 == key_bits && kpt == KPTV)                                                                  \
+    return msd_sort_impl<KT, KPTV>(reinterpret_cast<KT*>(keys), idx, L, w, count_dev, (uint32_t)n_max, gather_in, \
+                                   gather_out, gather_n, st, ksrc);
+  RR_MSD_CASE(uint32_t, 16)
+  RR_MSD_CASE(uint32_t, 8)
+  RR_MSD_CASE(uint64_t, 16)
+  RR_MSD_CASE(uint64_t, 8)
+#undef RR_MSD_CASE
+  return RR_ERR_UNSUPPORTED;
+}
+
+}  // namespace
+
+rr_status launch_sort_auto(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                           void* ws, size_t ws_bytes, hipStream_t st) {
+  if (key_bits != 32 && key_bits != 64) return RR_ERR_UNSUPPORTED;
+  const uint32_t kpt = sort_default_kpt(n_max);
+  if (msd_preferred(n_max, key_bits))
+    return launch_msd(keys, idx, n_max, count_dev, key_bits, kpt, ws, ws_bytes, nullptr, nullptr, 0u, st, nullptr);
+  return launch_sort(keys, idx, n_max, count_dev, key_bits, 8, kpt, ws, ws_bytes, st);
+}
+
 rr_status launch_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                       uint32_t db, uint32_t kpt, void* ws, size_t ws_bytes, hipStream_t st) {
   if (!sort_config_supported(key_bits, db, kpt)) return RR_ERR_UNSUPPORTED;
@@ -816,9 +1396,11 @@ rr_status launch_keys_sort_gather(const rr_ray* rays, int64_t n, const KeyPlan& 
   if (n <= 0) return RR_OK;
   if (!sort_config_supported(key_bits, 8, kpt) || (plan.key64 && key_family(plan.kind) == 3))
     return RR_ERR_UNSUPPORTED;
+  const KeySource src{rays, plan};
+  if (msd_preferred(n, key_bits))
+    return launch_msd(keys, idx, n, nullptr, key_bits, kpt, ws, ws_bytes, rays, rays_out, (uint32_t)n, st, &src);
   const SegLayout L = seg_layout(n, 1, key_bits, 8, kpt);
   if (ws_bytes < L.total) return RR_ERR_WORKSPACE_TOO_SMALL;
-  const KeySource src{rays, plan};
   char* w = reinterpret_cast<char*>(ws);
 #define RR_KSORT_CASE(KT, KPTV)                                                                              \
   if (sizeof(KT) * 8 == key_bits && kpt == KPTV)                                                           \
@@ -836,6 +1418,9 @@ rr_status launch_sort_gather(void* keys, uint32_t* idx, int64_t n_max, const uin
                              uint32_t db, uint32_t kpt, void* ws, size_t ws_bytes, const rr_ray* rays_in,
                              rr_ray* rays_out, hipStream_t st) {
   if (!sort_config_supported(key_bits, db, kpt)) return RR_ERR_UNSUPPORTED;
+  if (db == 8 && msd_preferred(n_max, key_bits))
+    return launch_msd(keys, idx, n_max, count_dev, key_bits, kpt, ws, ws_bytes, rays_in, rays_out, (uint32_t)n_max, st,
+                      nullptr);
   const SegLayout L = seg_layout(n_max, 1, key_bits, db, kpt);
   if (ws_bytes < L.total) return RR_ERR_WORKSPACE_TOO_SMALL;
   return launch_seg_sort(keys, idx, L, ws, nullptr, nullptr, count_dev, (uint32_t)n_max, key_bits, db, kpt, false,

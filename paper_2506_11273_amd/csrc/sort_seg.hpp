@@ -16,15 +16,36 @@ struct SortHdr {
   uint32_t nseg, total_tiles, total_keys, pad;
 };
 
+// Digits chosen on the device for the most-significant-digit sort: dh the
+// highest 8-bit digit in which the keys differ, dl the next one below it
+// (any other digit when no lower one differs).
+struct MsdPlan {
+  uint32_t dh, dl, n, pad;
+};
+
 // hist holds hist_copies copies of every segment's digit histograms
 // (passes x radix words each); a single-segment sort spreads its histogram
 // flush over several copies, summed again by the scatter passes.
+// The most-significant-digit sort (msd) adds: the plan, a header and 256
+// segments (one per value of digit dh), their digit-dl histograms (hist2,
+// 256 x 256 words, also the bucket sizes), the start of every (dh, dl)
+// bucket (bstart), and look-back words for its two passes (status2, two
+// passes of status2_stride words; gstatus2 likewise).
 struct SegLayout {
   size_t keys_alt, idx_alt, hdr, segs, hist, counters, status, gstatus, total;
+  size_t plan, hdr2, segs2, hist2, bstart, status2, gstatus2;
   uint32_t passes, tile, max_seg, max_tiles, status_stride, gstatus_stride, hist_copies;
+  uint32_t status2_stride, gstatus2_stride;
+  bool msd;
 };
 
 SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_t db, uint32_t kpt);
+// Layout of the single-segment most-significant-digit sort (8-bit digits,
+// kpt keys per thread in its two scatter passes).
+SegLayout msd_layout(int64_t n_max, uint32_t key_bits, uint32_t kpt);
+// Whether rr_sort and the fused call take the most-significant-digit sort
+// for a capacity of n_max keys of key_bits bits (else the LSD sort).
+bool msd_preferred(int64_t n_max, uint32_t key_bits);
 
 // Sorts every segment described by the device header and segment table
 // hdr / segs.  With hdr == nullptr one segment of min(*count_dev, n_max)
