@@ -339,6 +339,26 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
                                const rr_key_params* p, rr_hit* hits, uint32_t* perm_out, uint32_t* count_out,
                                uint32_t flags, void* workspace, size_t ws_bytes, void* stream);
 
+/* --------------------------------------------------- without allocation
+ * For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * rr_reorder_and_trace with its workspace in a static device array of
+ * RR_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends.  Arguments, results and errors are those of
+ * rr_reorder_and_trace without the workspace; the call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine).  A call whose
+ * workspace (rr_reorder_workspace_size) exceeds the array is rejected with
+ * RR_ERR_WORKSPACE_TOO_SMALL before anything is enqueued: the limit is
+ * about 2.25M rays with 64-bit keys and 2.5M with 32-bit keys (or none).
+ * All calls on one GPU share that GPU's array; every call initialises what
+ * it reads, but calls that overlap on one GPU (other streams or threads
+ * without ordering between them) race and must be serialised by the
+ * caller.  The first call on a device looks the array's address up. */
+#define RR_NOALLOC_SCRATCH_BYTES ((size_t)160 << 20)
+rr_status rr_reorder_and_trace_noalloc(rr_scene s, const rr_ray* rays, int64_t n, const uint8_t* alive,
+                                       const rr_key_params* p, rr_hit* hits, uint32_t* perm_out,
+                                       uint32_t* count_out, uint32_t flags, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

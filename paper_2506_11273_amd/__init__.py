@@ -15,7 +15,7 @@ from .rr import (  # noqa: F401
     RR_LENGTH_CELLS, RR_HITS_ORIGINAL_ORDER, RR_INDIRECT, RR_LOCAL_SORT_1024, RR_LOCAL_SORT_2048,
     RR_LOCAL_SORT_4096, RR_ANY_HIT, LengthTable,
     coherence_m64, hits_to_numpy, key_params, keys_workspace_size, load, reorder_workspace_size, sort_workspace_size,
-    rr_compute_keys, rr_sort, rr_local_sort, rr_gather, rr_scatter_hits, rr_trace, rr_trace_any, rr_trace_profile, rr_reorder_and_trace,
+    rr_compute_keys, rr_sort, rr_local_sort, rr_gather, rr_scatter_hits, rr_trace, rr_trace_any, rr_trace_profile, rr_reorder_and_trace, rr_reorder_and_trace_noalloc,
     workspace,
 )
 from .batch import (  # noqa: F401

@@ -21,7 +21,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librr.so")
 
-SOURCES = ["keys.hip", "sort.hip", "local_sort.hip", "gather.hip", "trace.hip", "coherence.hip", "batch.hip", "scene.cpp", "api.cpp", "serve.cpp"]
+SOURCES = ["keys.hip", "sort.hip", "local_sort.hip", "gather.hip", "trace.hip", "coherence.hip", "batch.hip",
+           "noalloc.hip", "scene.cpp", "api.cpp", "serve.cpp"]
 ARCH = os.environ.get("RR_OFFLOAD_ARCH", "gfx950")
 
 

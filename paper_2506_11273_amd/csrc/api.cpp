@@ -356,9 +356,15 @@ rr_status rr_reorder_workspace_size(int64_t n_max, const rr_key_params* p, size_
   return RR_OK;
 }
 
-rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const uint8_t* alive,
-                               const rr_key_params* p, rr_hit* hits, uint32_t* perm_out, uint32_t* count_out,
-                               uint32_t flags, void* workspace, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// rr_reorder_and_trace; ws_is_scratch: the workspace is the library's own
+// static device array (its size checked by the caller), not caller memory.
+rr_status reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const uint8_t* alive,
+                            const rr_key_params* p, rr_hit* hits, uint32_t* perm_out, uint32_t* count_out,
+                            uint32_t flags, void* workspace, size_t ws_bytes, void* stream, bool ws_is_scratch) {
   if (!s || !p || !valid_n(n)) return RR_ERR_INVALID_ARGUMENT;
   constexpr uint32_t kLocal = RR_LOCAL_SORT_1024 | RR_LOCAL_SORT_2048 | RR_LOCAL_SORT_4096;
   if (flags & ~(RR_HITS_ORIGINAL_ORDER | RR_INDIRECT | RR_ANY_HIT | kLocal)) return RR_ERR_INVALID_ARGUMENT;
@@ -388,7 +394,8 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
   if (hipGetDevice(&dev) != hipSuccess || dev != s->d.device) return RR_ERR_INVALID_ARGUMENT;
   const uint32_t kb = sorted ? p->key_bits : 32u;
   const ReorderLayout L = reorder_layout(n, kb);
-  if (!workspace || !is_device_ptr(workspace) || !aligned(workspace, 256)) return RR_ERR_INVALID_ARGUMENT;
+  if (!workspace || (!ws_is_scratch && !is_device_ptr(workspace)) || !aligned(workspace, 256))
+    return RR_ERR_INVALID_ARGUMENT;
   if (ws_bytes < L.total) return RR_ERR_WORKSPACE_TOO_SMALL;
 
   char* w = reinterpret_cast<char*>(workspace);
@@ -461,6 +468,29 @@ rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const 
     }
   }
   return RR_OK;
+}
+
+}  // namespace
+
+namespace rr {
+
+rr_status reorder_and_trace_in_scratch(rr_scene s, const rr_ray* rays, int64_t n, const uint8_t* alive,
+                                       const rr_key_params* p, rr_hit* hits, uint32_t* perm_out,
+                                       uint32_t* count_out, uint32_t flags, void* scratch, size_t scratch_bytes,
+                                       void* stream) {
+  return reorder_and_trace(s, rays, n, alive, p, hits, perm_out, count_out, flags, scratch, scratch_bytes, stream,
+                           true);
+}
+
+}  // namespace rr
+
+extern "C" {
+
+rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const uint8_t* alive,
+                               const rr_key_params* p, rr_hit* hits, uint32_t* perm_out, uint32_t* count_out,
+                               uint32_t flags, void* workspace, size_t ws_bytes, void* stream) {
+  return reorder_and_trace(s, rays, n, alive, p, hits, perm_out, count_out, flags, workspace, ws_bytes, stream,
+                           false);
 }
 
 }  // extern "C"

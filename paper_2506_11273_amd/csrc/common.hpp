@@ -145,6 +145,13 @@ rr_status launch_trace_any(const DeviceScene& s, const rr_ray* rays, const uint3
 rr_status launch_trace(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
                        const uint32_t* count_dev, rr_hit* hits, hipStream_t st);
 
+// rr_reorder_and_trace with a workspace that is the library's static
+// device array (scratch_bytes long, already known to be device memory).
+rr_status reorder_and_trace_in_scratch(rr_scene_s* s, const rr_ray* rays, int64_t n, const uint8_t* alive,
+                                       const rr_key_params* p, rr_hit* hits, uint32_t* perm_out,
+                                       uint32_t* count_out, uint32_t flags, void* scratch, size_t scratch_bytes,
+                                       void* stream);
+
 }  // namespace rr
 
 struct rr_scene_s {

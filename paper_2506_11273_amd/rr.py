@@ -59,7 +59,7 @@ EXPORTS = (
     "rr_coherence_m64",
     "rr_sort_workspace_size", "rr_sort", "rr_sort_ex", "rr_local_sort",
     "rr_gather", "rr_scatter_hits", "rr_trace", "rr_trace_ex", "rr_trace_any", "rr_trace_profile",
-    "rr_reorder_workspace_size", "rr_reorder_and_trace",
+    "rr_reorder_workspace_size", "rr_reorder_and_trace", "rr_reorder_and_trace_noalloc",
 )
 
 
@@ -116,6 +116,7 @@ def load():
         "rr_trace_ex": ([vp, vp, i64, vp, vp, u32, vp], st),
         "rr_reorder_workspace_size": ([i64, P(KeyParams), P(sz)], st),
         "rr_reorder_and_trace": ([vp, vp, i64, vp, P(KeyParams), vp, vp, vp, u32, vp, sz, vp], st),
+        "rr_reorder_and_trace_noalloc": ([vp, vp, i64, vp, P(KeyParams), vp, vp, vp, u32, vp], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -446,6 +447,24 @@ def rr_reorder_and_trace(scene: Scene, rays, params: KeyParams, alive=None, flag
                                   _ptr(hits, "hits", torch.float32), _ptr(perm, "perm", torch.int32, False),
                                   _ptr(count, "count", torch.int32, False), flags, _ptr(ws, "workspace"),
                                   ws.numel() * ws.element_size(), _stream(stream)), "rr_reorder_and_trace")
+    return hits, perm, count
+
+
+def rr_reorder_and_trace_noalloc(scene: Scene, rays, params: KeyParams, alive=None,
+                                 flags: int = RR_HITS_ORIGINAL_ORDER, hits=None, perm=None, count=None,
+                                 stream=None):
+    """rr_reorder_and_trace with the library's static device workspace (no
+    device allocation inside the call); outputs the caller did not pass are
+    allocated here, before the call.  Returns (hits, perm, count)."""
+    torch = _torch()
+    n = _n_rows(rays)
+    hits = torch.empty((n, 4), dtype=torch.float32, device=rays.device) if hits is None else hits
+    _check(load().rr_reorder_and_trace_noalloc(scene.handle, _ptr(rays, "rays", torch.float32), n,
+                                               _ptr(alive, "alive", torch.uint8, False), ctypes.byref(params),
+                                               _ptr(hits, "hits", torch.float32),
+                                               _ptr(perm, "perm", torch.int32, False),
+                                               _ptr(count, "count", torch.int32, False), flags, _stream(stream)),
+           "rr_reorder_and_trace_noalloc")
     return hits, perm, count
 
 
