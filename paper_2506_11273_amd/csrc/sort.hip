@@ -713,7 +713,9 @@ template <typename K>
 struct LocSmem {
   K keys[kLocCap];
   uint32_t idx[kLocCap];
-  uint32_t wave_hist[kLocWaves][256];
+  // per-wave digit counts, then each wave's exclusive prefix per digit; two
+  // buffers used in turn, each cleared while the other one is in use
+  uint32_t wave_hist[2][kLocWaves][256];
   uint32_t base[256];           // exclusive digit offsets of the last ranking
   uint32_t cnt[256];            // digit counts of the last ranking
   uint32_t run[256];            // large bucket: next output position per digit
@@ -746,20 +748,42 @@ __device__ __forceinline__ uint32_t block_scan_n(uint32_t v, uint32_t* s, uint32
   return pre + x - v;
 }
 
+// Exclusive scan over the 64 lanes of a wave; *total receives the sum.
+__device__ __forceinline__ uint32_t wave_scan_excl(uint32_t v, uint32_t* total) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, kWave);
+    if (lane >= (uint32_t)off) x += y;
+  }
+  *total = __shfl(x, kWave - 1, kWave);
+  return x - v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) v = max(v, (uint32_t)__shfl_xor(v, off, kWave));
+  return v;
+}
+
 // Position of element j of this thread in a batch: waves own kLocKpt
 // consecutive groups of 64.
 __device__ __forceinline__ uint32_t loc_pos(int j) {
   return ((threadIdx.x / kWave) * kLocKpt + (uint32_t)j) * kWave + (threadIdx.x & (kWave - 1));
 }
 
-// Stable ranking by the 8-bit digits dg of the batch positions below nb:
-// pos[j] receives the place of element j in the order by digit that keeps
-// equal digits in position order.  Leaves the digit counts in sm.cnt and
-// their exclusive offsets in sm.base; sm.wave_hist is zero on entry and on
-// return.
+// Stable ranking by the 8-bit digits dg of the batch positions below nb,
+// with counter buffer buf (zero on entry): pos[j] receives the place of
+// element j in the order by digit that keeps equal digits in position
+// order.  Leaves the digit counts in sm.cnt and their exclusive offsets in
+// sm.base.  The caller synchronises the block after its last use of pos
+// and then clears buffer buf (loc_clear) before that buffer's next ranking.
 template <typename K>
-__device__ void loc_rank(LocSmem<K>& sm, const uint32_t (&dg)[kLocKpt], uint32_t nb, uint32_t (&pos)[kLocKpt]) {
+__device__ void loc_rank(LocSmem<K>& sm, uint32_t buf, const uint32_t (&dg)[kLocKpt], uint32_t nb,
+                         uint32_t (&pos)[kLocKpt]) {
   const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  uint32_t (*wh)[256] = sm.wave_hist[buf];
   uint32_t rank[kLocKpt], old[kLocKpt];
 #pragma unroll
   for (int j = 0; j < kLocKpt; ++j) {
@@ -768,46 +792,63 @@ __device__ void loc_rank(LocSmem<K>& sm, const uint32_t (&dg)[kLocKpt], uint32_t
     const uint32_t leader = ok ? (uint32_t)__builtin_ctzll(peers) : lane;
     rank[j] = lanes_below(peers) | (leader << 16);
     old[j] = 0;
-    if (ok && lane == leader) old[j] = atomicAdd(&sm.wave_hist[wave][dg[j]], (uint32_t)__popcll(peers));
+    if (ok && lane == leader) old[j] = atomicAdd(&wh[wave][dg[j]], (uint32_t)__popcll(peers));
   }
 #pragma unroll
   for (int j = 0; j < kLocKpt; ++j) rank[j] = (rank[j] & 0xFFFFu) + __shfl(old[j], (int)(rank[j] >> 16), kWave);
   __syncthreads();
-  // per digit: the waves' exclusive prefixes in place, then the digit offset
-  uint32_t c = 0;
-  if (tid < 256) {
+  if (wave == 0) {
+    // lane l takes digits l, l + 64, l + 128, l + 192: each wave's count
+    // becomes its exclusive prefix over the waves, then the digit totals
+    // are scanned in digit order
+#pragma unroll 1
+    for (uint32_t q = 0; q < 4; ++q) {
+      const uint32_t d = lane + 64u * q;
+      uint32_t t[kLocWaves];
 #pragma unroll
-    for (int w = 0; w < kLocWaves; ++w) {
-      const uint32_t t = sm.wave_hist[w][tid];
-      sm.wave_hist[w][tid] = c;
-      c += t;
+      for (int w = 0; w < kLocWaves; ++w) t[w] = wh[w][d];
+      uint32_t acc = 0;
+#pragma unroll
+      for (int w = 0; w < kLocWaves; ++w) {
+        wh[w][d] = acc;
+        acc += t[w];
+      }
+      sm.cnt[d] = acc;
     }
-  }
-  uint32_t total;
-  const uint32_t ex = block_scan_n<kLocWaves>(tid < 256 ? c : 0u, sm.scan, &total);
-  if (tid < 256) {
-    sm.base[tid] = ex;
-    sm.cnt[tid] = c;
+    uint32_t c[4], e[4], g[4];
 #pragma unroll
-    for (int w = 0; w < kLocWaves; ++w) sm.wave_hist[w][tid] += ex;
+    for (int q = 0; q < 4; ++q) c[q] = sm.cnt[lane + 64u * (uint32_t)q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) e[q] = wave_scan_excl(c[q], &g[q]);
+    uint32_t b = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sm.base[lane + 64u * (uint32_t)q] = b + e[q];
+      b += g[q];
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < kLocKpt; ++j)
-    if (loc_pos(j) < nb) pos[j] = sm.wave_hist[wave][dg[j]] + rank[j];
-  __syncthreads();
-  for (uint32_t i = tid; i < kLocWaves * 256; i += kLocThreads) (&sm.wave_hist[0][0])[i] = 0;
-  __syncthreads();
+    if (loc_pos(j) < nb) pos[j] = sm.base[dg[j]] + wh[wave][dg[j]] + rank[j];
+}
+
+// Clears counter buffer buf (after a block synchronisation that follows its
+// last use).
+template <typename K>
+__device__ __forceinline__ void loc_clear(LocSmem<K>& sm, uint32_t buf) {
+  for (uint32_t i = threadIdx.x; i < kLocWaves * 256; i += kLocThreads) (&sm.wave_hist[buf][0][0])[i] = 0;
 }
 
 // One stable pass of a batch in LDS: the elements held in registers move to
 // their places in the order by dg, and each thread then holds the elements
-// of its positions again.
+// of its positions again.  Uses counter buffer buf, which it clears, and
+// flips buf for the next pass.
 template <typename K>
-__device__ void loc_pass(LocSmem<K>& sm, K (&k)[kLocKpt], uint32_t (&v)[kLocKpt], const uint32_t (&dg)[kLocKpt],
-                         uint32_t nb) {
+__device__ void loc_pass(LocSmem<K>& sm, uint32_t& buf, K (&k)[kLocKpt], uint32_t (&v)[kLocKpt],
+                         const uint32_t (&dg)[kLocKpt], uint32_t nb) {
   uint32_t pos[kLocKpt];
-  loc_rank(sm, dg, nb, pos);
+  loc_rank(sm, buf, dg, nb, pos);
 #pragma unroll
   for (int j = 0; j < kLocKpt; ++j) {
     if (loc_pos(j) < nb) {
@@ -824,7 +865,10 @@ __device__ void loc_pass(LocSmem<K>& sm, K (&k)[kLocKpt], uint32_t (&v)[kLocKpt]
       v[j] = sm.idx[p];
     }
   }
-  __syncthreads();
+  loc_clear(sm, buf);
+  buf ^= 1u;
+  // the next pass writes sm.keys only after the synchronisation inside its
+  // ranking, when every thread has read its elements back
 }
 
 // The ray gather of the fused call for sorted positions [i0, i1).
@@ -846,9 +890,10 @@ __device__ __forceinline__ void loc_gather_one(const float4* __restrict__ in, fl
 // chunk by chunk in position order, between the buffers and the alternate
 // buffers at the same positions.
 template <typename K>
-__device__ void loc_big(LocSmem<K>& sm, K* __restrict__ keys, uint32_t* __restrict__ idx, K* __restrict__ kalt,
-                        uint32_t* __restrict__ ialt, uint32_t r0, uint32_t m, uint32_t dh, uint32_t dl,
-                        const float4* __restrict__ gather_in, float4* __restrict__ gather_out, uint32_t gather_n) {
+__device__ void loc_big(LocSmem<K>& sm, uint32_t& buf, K* __restrict__ keys, uint32_t* __restrict__ idx,
+                        K* __restrict__ kalt, uint32_t* __restrict__ ialt, uint32_t r0, uint32_t m, uint32_t dh,
+                        uint32_t dl, const float4* __restrict__ gather_in, float4* __restrict__ gather_out,
+                        uint32_t gather_n) {
   constexpr uint32_t P = sizeof(K);
   const uint32_t tid = threadIdx.x;
   for (uint32_t i = tid; i < P * 256; i += kLocThreads) (&sm.fh[0][0])[i] = 0;
@@ -883,7 +928,7 @@ __device__ void loc_big(LocSmem<K>& sm, K* __restrict__ keys, uint32_t* __restri
         v[j] = p < nb ? si[c0 + p] : 0u;
         dg[j] = (uint32_t)(k[j] >> (8 * d)) & 255u;
       }
-      loc_rank(sm, dg, nb, pos);
+      loc_rank(sm, buf, dg, nb, pos);
 #pragma unroll
       for (int j = 0; j < kLocKpt; ++j) {
         if (loc_pos(j) < nb) {
@@ -893,6 +938,8 @@ __device__ void loc_big(LocSmem<K>& sm, K* __restrict__ keys, uint32_t* __restri
         }
       }
       __syncthreads();
+      loc_clear(sm, buf);
+      buf ^= 1u;
       if (tid < 256) sm.run[tid] += sm.cnt[tid];
       __syncthreads();
     }
@@ -925,9 +972,10 @@ __global__ __launch_bounds__(kLocThreads) void k_msd_local(K* __restrict__ keys,
   const uint32_t wb = blockIdx.x * kLocWindow;
   if (wb >= n) return;
   const uint32_t we = min(n, wb + kLocWindow);
-  const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < kLocWaves * 256; i += kLocThreads) (&sm.wave_hist[0][0])[i] = 0;
+  const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1);
+  for (uint32_t i = tid; i < 2 * kLocWaves * 256; i += kLocThreads) (&sm.wave_hist[0][0][0])[i] = 0;
   __syncthreads();
+  uint32_t buf = 0;  // counter buffer of the next ranking
   const uint32_t dh = plan->dh, dl = plan->dl;
   const uint32_t sh = dh * 8, sl = dl * 8;
   auto bucket = [&](K x) -> uint32_t { return (((uint32_t)(x >> sh) & 255u) << 8) | ((uint32_t)(x >> sl) & 255u); };
@@ -971,7 +1019,8 @@ __global__ __launch_bounds__(kLocThreads) void k_msd_local(K* __restrict__ keys,
         }
       }
     }
-    if (cand) atomicMax(&sm.red[0], cand);
+    cand = wave_max(cand);
+    if (lane == 0 && cand) atomicMax(&sm.red[0], cand);
     __syncthreads();
     const uint32_t nb = sm.red[0];
     if (nb == 0) {
@@ -979,35 +1028,36 @@ __global__ __launch_bounds__(kLocThreads) void k_msd_local(K* __restrict__ keys,
       // keys that remain, so that every access stays in range)
       const uint32_t m = max(1u, min(bcount[b0], n - p0));
       __syncthreads();
-      loc_big(sm, keys, idx, kalt, ialt, p0, m, dh, dl, gather_in, gather_out, gather_n);
+      loc_big(sm, buf, keys, idx, kalt, ialt, p0, m, dh, dl, gather_in, gather_out, gather_n);
       p0 += m;
       continue;
     }
-    // digits in which the batch's keys differ, and its bucket span
+    // digits in which the batch's keys differ (one bit per digit, one LDS
+    // atomic per wave), and its bucket span: bucket numbers ascend with the
+    // position, so the last element's bucket gives it
     uint64_t diff = 0;
-    uint32_t rspan = 0;
 #pragma unroll
     for (int j = 0; j < kLocKpt; ++j) {
-      if (loc_pos(j) < nb) {
-        diff |= (uint64_t)(k[j] ^ kfirst);
-        rspan = max(rspan, bucket(k[j]) - b0);
-      }
+      const uint32_t p = loc_pos(j);
+      if (p < nb) diff |= (uint64_t)(k[j] ^ kfirst);
+      if (p + 1 == nb) sm.red[3] = bucket(k[j]) - b0;
     }
-    if ((uint32_t)diff) atomicOr(&sm.red[1], (uint32_t)diff);
-    if ((uint32_t)(diff >> 32)) atomicOr(&sm.red[2], (uint32_t)(diff >> 32));
-    if (rspan) atomicMax(&sm.red[3], rspan);
+    uint32_t dmask = 0;
+#pragma unroll
+    for (uint32_t d = 0; d < P; ++d)
+      if (__ballot(((diff >> (8 * d)) & 255u) != 0)) dmask |= 1u << d;
+    if (lane == 0 && dmask) atomicOr(&sm.red[1], dmask);
     __syncthreads();
-    const uint64_t dm = (uint64_t)sm.red[1] | ((uint64_t)sm.red[2] << 32);
+    const uint32_t dm = sm.red[1];
     const uint32_t span = sm.red[3];
-    __syncthreads();
     bool moved = false;
     uint32_t dg[kLocKpt];
 #pragma unroll 1
     for (uint32_t d = 0; d < P; ++d) {
-      if (d == dh || d == dl || ((dm >> (8 * d)) & 255u) == 0) continue;
+      if (d == dh || d == dl || ((dm >> d) & 1u) == 0) continue;
 #pragma unroll
       for (int j = 0; j < kLocKpt; ++j) dg[j] = (uint32_t)(k[j] >> (8 * d)) & 255u;
-      loc_pass(sm, k, v, dg, nb);
+      loc_pass(sm, buf, k, v, dg, nb);
       moved = true;
     }
     // keys equal in every other digit are still in bucket order
@@ -1016,7 +1066,7 @@ __global__ __launch_bounds__(kLocThreads) void k_msd_local(K* __restrict__ keys,
       for (uint32_t q = 0; q < (span > 255 ? 16u : 8u); q += 8) {
 #pragma unroll
         for (int j = 0; j < kLocKpt; ++j) dg[j] = ((bucket(k[j]) - b0) >> q) & 255u;
-        loc_pass(sm, k, v, dg, nb);
+        loc_pass(sm, buf, k, v, dg, nb);
       }
     }
 #pragma unroll
