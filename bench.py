@@ -46,7 +46,7 @@ TRAFFIC_PROFILE = os.path.join("profiles", "k_trace4_bounce2_1080p_traffic.txt")
 TRAFFIC_SOURCES = ("paper_2506_11273_amd/csrc/trace.hip", "paper_2506_11273_amd/csrc/scene.cpp",
                    "paper_2506_11273_amd/csrc/common.hpp", "paper_2506_11273_amd/csrc/keys_dev.hpp",
                    "paper_2506_11273_amd/csrc/keys.hip", "workloads/gen.c")
-SECTIONS = ("variants", "orders", "shuffled", "shadow", "bounce3", "sorts", "batch", "serve", "cpu")
+SECTIONS = ("config1", "variants", "orders", "shuffled", "shadow", "bounce3", "sorts", "batch", "serve", "cpu")
 
 
 def parse(argv=None):
@@ -252,6 +252,8 @@ def main():
         "roofline": trace_roofline(trace_bytes, trace_ms, n, profiled_traffic(args.key, args.builder),
                                    profiled_valu(args.key, args.builder), prof["inner_visits"], prof["tri_tests"]),
     }
+    if "config1" not in args.skip:
+        result["config1_soup_65k"] = config1(torch, rr, W, dev, stream)
     if "variants" not in args.skip:
         result["variants"] = variants(torch, rr, scene, rays, n, lo, hi, dev, stream, args.steps, unsorted_ms, uhits)
     if "orders" not in args.skip:
@@ -273,6 +275,9 @@ def main():
         main_load = min(result["served"]["loads"], key=lambda r: abs(r["offered_load"] - 0.8))
         result["p50_ms"] = main_load["p50_ms"]
         result["p99_ms"] = main_load["p99_ms"]
+        base = min(result["served"]["unsorted_loads"], key=lambda r: abs(r["offered_load"] - 0.8))
+        result["unsorted_served_p50_ms"] = base["p50_ms"]
+        result["unsorted_served_p99_ms"] = base["p99_ms"]
     if "cpu" not in args.skip:
         result["cpu_baseline"] = cpu_baseline(w, args.key)
     if args.copy_calibration:
@@ -361,6 +366,48 @@ def trace_roofline(trace_bytes, trace_ms, n, traffic, valu_instr, inner_visits=N
     r["valu_wave_instructions"] = valu_instr
     r["valu_wave_instructions_per_ray"] = round(valu_instr / n, 1) if valu_instr else None
     return r
+
+
+def config1(torch, rr, W, dev, stream, reps=50):
+    """The small configuration of the method: 65,536 rays (origins uniform
+    in the unit cube, directions uniform on the sphere) against 4,096 random
+    triangles, median-split BVH, 32-bit origin-direction keys.  Per fused
+    call: device time (HIP events, median), wall time per call with the
+    calls issued back to back, and the host time to issue one call (no
+    synchronisation inside the issuing loop); the unsorted trace alike."""
+    w = W.soup(seed=1)
+    n = w.rays.shape[0]
+    out = {"rays": int(n), "triangles": int(w.tris.shape[0]), "bvh": "median split collapsed to 4-wide",
+           "key": "od32"}
+    with rr.Scene(w.tris, builder=0) as sc:
+        lo, hi = sc.bounds()
+        p = rr.key_params(1, 32, lo, hi, 0.25)
+        rays = torch.from_numpy(w.rays).to(dev)
+        hits = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        ws = rr.workspace(rr.reorder_workspace_size(n, p), dev)
+
+        def fused():
+            rr.rr_reorder_and_trace(sc, rays, p, flags=0, hits=hits, ws=ws, want_perm=False, want_count=False)
+
+        def unsorted():
+            rr.rr_trace(sc, rays, hits=hits)
+
+        for name, fn in (("fused", fused), ("unsorted_trace", unsorted)):
+            for _ in range(5):
+                fn()
+            dev_ms = median_ms(torch, stream, fn, reps)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            t1 = time.perf_counter()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            out[name] = {"device_ms": round(dev_ms, 4), "mrays": round(n / (dev_ms * 1e-3) / 1e6, 2),
+                         "wall_ms_per_call": round((t2 - t0) * 1e3 / reps, 4),
+                         "host_issue_us_per_call": round((t1 - t0) * 1e6 / reps, 1)}
+        out["reorder_vs_unsorted"] = round(out["unsorted_trace"]["device_ms"] / out["fused"]["device_ms"], 3)
+    return out
 
 
 def variants(torch, rr, scene, rays, n, lo, hi, dev, stream, steps, unsorted_ms, uhits):
@@ -746,6 +793,15 @@ def batched(torch, rr, W, scene, w, dev, stream):
         ms = median_ms(torch, stream, lambda: b.run(segs, flags=0), 10)
         out["graph_ms"] = round(ms, 3)
         out["mrays"] = round(total / (ms * 1e-3) / 1e6, 2)
+        # the same graph with every segment unsorted (key kind none): the
+        # same-form baseline of the reordered batch
+        none = rr.key_params(0, 32, *scene.bounds())
+        usegs = [rr.segment(r, h, none) for r, h in keep]
+        b.run(usegs, flags=0)
+        ms_n = median_ms(torch, stream, lambda: b.run(usegs, flags=0), 10)
+        out["graph_unsorted_ms"] = round(ms_n, 3)
+        out["graph_unsorted_mrays"] = round(total / (ms_n * 1e-3) / 1e6, 2)
+        out["graph_reorder_vs_unsorted"] = round(ms_n / ms, 3)
         ms_o = median_ms(torch, stream, lambda: b.run(segs, flags=rr.RR_HITS_ORIGINAL_ORDER), 5)
         out["graph_scatter_back_ms"] = round(ms_o, 3)
         # the same wavefronts one call each
@@ -760,6 +816,13 @@ def batched(torch, rr, W, scene, w, dev, stream):
         ms_p = median_ms(torch, stream, per_call, 3)
         out["per_call_ms"] = round(ms_p, 3)
         out["per_call_mrays"] = round(total / (ms_p * 1e-3) / 1e6, 2)
+        # host time to issue the 64 calls (no synchronisation in between)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        per_call()
+        t1 = time.perf_counter()
+        torch.cuda.synchronize()
+        out["per_call_host_issue_ms"] = round((t1 - t0) * 1e3, 3)
         # unsorted trace of the same rays, one call each
         def unsorted():
             for (rays, hits) in keep:
@@ -769,13 +832,25 @@ def batched(torch, rr, W, scene, w, dev, stream):
     return out
 
 
+# the server's shape in the served section: 4 slots, requests in ray order
+# above 512K rays served as parts of 512K
+SERVE_SHAPE = dict(slots=4, hbm_budget_bytes=32 << 30, max_batch_rays=1 << 23, max_batch_requests=16,
+                   split_rays=1 << 19)
+# the earlier shape (2 slots, no parts), run at 0.8 load for comparison
+SERVE_SHAPE_2SLOTS = dict(slots=2, hbm_budget_bytes=32 << 30, max_batch_rays=1 << 23, max_batch_requests=16,
+                          split_rays=0)
+
+
 def served(torch, rr, W, dev, n_req, loads):
     """Poisson streams of requests (ray counts log-uniform in [16K, 4M], key
     kind drawn per request from none / OD-32 / OD-64 / OT-64, rays drawn
     from the primary, bounce-1 and bounce-2 rays of a 3840x2160 view) against
     the grid city scaled 2x2 (~4M triangles), served with continuous
-    batching on 2 streams under a 32 GB workspace budget, at each offered
-    load (a fraction of the measured batched capacity)."""
+    batching (SERVE_SHAPE) under a 32 GB workspace budget, at each offered
+    load (a fraction of the measured batched capacity).  The same stream
+    with every request unsorted (key kind none) is served at the same loads
+    and arrival times: the same-form baseline; and the mixed stream with the
+    2-slot shape without parts at 0.8 load."""
     c = W.city(5, 200, 200, 3_520_000)
     scene = rr.Scene(c.tris)
     lo, hi = scene.bounds()
@@ -786,6 +861,7 @@ def served(torch, rr, W, dev, n_req, loads):
         r, alive = W.bounce(c, 5, 300 + k, r, alive)
         pools.append(torch.from_numpy(np.ascontiguousarray(r[alive.astype(bool)])).to(dev))
     kinds = ["none", "od32", "od64", "ot64"]
+    none = rr.key_params(0, 32, lo, hi, 0.25)
     warm = 50
     reqs = []
     for i in range(n_req + warm):
@@ -797,6 +873,7 @@ def served(torch, rr, W, dev, n_req, loads):
         hits = torch.empty((m, 4), dtype=torch.float32, device=dev)
         kind, bits = KEYS[kname]
         reqs.append((rays, hits, rr.key_params(kind, bits, lo, hi, 0.25), kname))
+    torch.cuda.synchronize()
     # batched capacity on this scene, to set the arrival rates
     segs = [rr.segment(a, b, k) for a, b, k, _ in reqs[warm:warm + 8]]
     stream = torch.cuda.current_stream()
@@ -805,27 +882,35 @@ def served(torch, rr, W, dev, n_req, loads):
         ms = median_ms(torch, stream, lambda: b.run(segs), 3)
     cap_rays_s = sum(int(s.n) for s in segs) / (ms * 1e-3)
     mean_n = float(np.mean([x[0].shape[0] for x in reqs[warm:]]))
-    out = {"scene_triangles": int(c.tris.shape[0]), "requests": n_req, "slots": 2,
-           "capacity_mrays": round(cap_rays_s / 1e6, 1), "mean_request_rays": int(mean_n), "loads": []}
-    cfg = dict(slots=2, hbm_budget_bytes=32 << 30, max_batch_rays=1 << 23, max_batch_requests=16)
-    with rr.Server(scene, **cfg) as sv:
-        sv.start()
-        for rays, hits, key, _ in reqs[:warm]:
-            sv.submit(rays, hits, key)
-        sv.drain(300.0)
-    for li, load in enumerate(loads):
+    out = {"scene_triangles": int(c.tris.shape[0]), "requests": n_req, "shape": SERVE_SHAPE,
+           "capacity_mrays": round(cap_rays_s / 1e6, 1), "mean_request_rays": int(mean_n), "loads": [],
+           "unsorted_loads": []}
+
+    def stream_run(cfg, load, li, unsorted):
         lam = load * cap_rays_s / mean_n
+        with rr.Server(scene, **cfg) as sv:
+            sv.start()
+            for rays, hits, key, _ in reqs[:warm]:
+                sv.submit(rays, hits, none if unsorted else key, sync=False)
+            sv.drain(300.0)
         with rr.Server(scene, **cfg) as sv:
             t = 0.02
             for i, (rays, hits, key, _) in enumerate(reqs[warm:]):
-                sv.submit(rays, hits, key, arrival_s=t)
+                sv.submit(rays, hits, none if unsorted else key, arrival_s=t, sync=False)
                 t += -math.log(1.0 - W.rngu(5, 60 + li, i)) / lam
             sv.start()
             sv.drain(600.0)
             st = sv.stats()
         row = {"offered_load": load, "arrival_rate_per_s": round(lam, 1)}
         row.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()})
-        out["loads"].append(row)
+        return row
+
+    for li, load in enumerate(loads):
+        out["loads"].append(stream_run(SERVE_SHAPE, load, li, False))
+        out["unsorted_loads"].append(stream_run(SERVE_SHAPE, load, li, True))
+    li8 = min(range(len(loads)), key=lambda i: abs(loads[i] - 0.8)) if loads else 0
+    if loads:
+        out["two_slots_no_parts_at_0.8"] = stream_run(SERVE_SHAPE_2SLOTS, loads[li8], li8, False)
     scene.close()
     return out
 

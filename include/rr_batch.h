@@ -95,7 +95,10 @@ typedef struct rr_server_config {
   int32_t slots;             /* concurrent batches (streams), >= 1 */
   int64_t hbm_budget_bytes;  /* device memory the server may hold for batch workspaces */
   int64_t max_batch_rays;    /* largest batch (and largest request) */
-  int32_t max_batch_requests;
+  int32_t max_batch_requests;  /* segments (requests or parts) per batch */
+  int64_t split_rays;        /* 0, or: a request in ray order larger than this is served as
+                                consecutive parts of at most split_rays rays, each reordered and
+                                traced as a segment of its own (its hits do not change) */
 } rr_server_config;
 
 typedef struct rr_request_stats {

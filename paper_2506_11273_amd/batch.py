@@ -51,7 +51,7 @@ class BatchConfig(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64), ("max_batch_rays", ctypes.c_int64),
-                ("max_batch_requests", ctypes.c_int32)]
+                ("max_batch_requests", ctypes.c_int32), ("split_rays", ctypes.c_int64)]
 
 
 class RequestStats(ctypes.Structure):
@@ -168,10 +168,10 @@ class Batch:
 
 class Server:
     def __init__(self, scene, slots: int = 2, hbm_budget_bytes: int = 32 << 30, max_batch_rays: int = 1 << 23,
-                 max_batch_requests: int = 64):
+                 max_batch_requests: int = 64, split_rays: int = 0):
         L = load()
         h = ctypes.c_void_p()
-        cfg = ServerConfig(slots, hbm_budget_bytes, max_batch_rays, max_batch_requests)
+        cfg = ServerConfig(slots, hbm_budget_bytes, max_batch_rays, max_batch_requests, split_rays)
         _check(L.rr_server_create(scene.handle, ctypes.byref(cfg), ctypes.byref(h)), "rr_server_create")
         self.handle = h
         self.scene = scene

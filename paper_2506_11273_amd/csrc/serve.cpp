@@ -7,9 +7,14 @@
 // records an event; a finished batch frees its slot, so requests that arrive
 // while others run start as soon as a slot is free and their work overlaps
 // on the device with the batches still running.  Slot workspaces are sized
-// so that all of them together stay within the HBM budget.  Every request's
-// hits come back in its ray order and equal those of the request traced
-// alone.
+// so that all of them together stay within the HBM budget.  A request
+// asking for hits in ray order that is larger than the server's split size
+// is served as consecutive parts of at most that many rays, each reordered
+// and traced as a segment of its own: parts of one request can run on
+// several slots at once and smaller requests fit in between, and since a
+// ray's hit does not depend on which rays it is traced with, the hits equal
+// those of the request traced alone.  Every request's hits come back in
+// the order it asked for and equal those of the request traced alone.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -35,7 +40,14 @@ struct Req {
   rr_hit* hits = nullptr;
   rr_key_params key{};
   uint32_t flags = 0;  // hit order: RR_HITS_ORIGINAL_ORDER or key order
-  int64_t bytes = 0;
+  int32_t parts_left = 0;
+};
+
+// A queued unit of work: rays [off, off + n) of a request.
+struct Part {
+  int64_t id;
+  int64_t off, n;
+  int64_t bytes;
 };
 
 struct Slot {
@@ -43,7 +55,7 @@ struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
-  std::vector<int64_t> reqs;
+  std::vector<int64_t> reqs;  // request of each part in the batch
   int64_t bytes = 0;
 };
 
@@ -61,7 +73,7 @@ struct rr_server_s {
   std::condition_variable done_cv;  // wakes waiters
   std::condition_variable gone_cv;  // wakes rr_server_destroy when the last waiter has left
   int32_t waiters = 0;              // threads inside rr_server_wait / rr_server_drain
-  std::deque<int64_t> pending;    // ids in arrival order
+  std::deque<Part> pending;       // parts in arrival order
   std::unordered_map<int64_t, Req> reqs;
   int64_t next_id = 1;
   int64_t inflight_bytes = 0, peak_inflight = 0;
@@ -85,12 +97,16 @@ bool device_ptr(const void* p, uintptr_t align) {
 
 double now_s(rr_server sv) { return std::chrono::duration<double>(clk::now() - sv->t0).count(); }
 
+// A batch finished: each of its parts is done; a request is done when its
+// last part is (with the first error any part met).
 void finish_slot(rr_server sv, Slot& s, rr_status status, double t) {
   for (int64_t id : s.reqs) {
     Req& r = sv->reqs[id];
-    r.st.done = 1;
-    r.st.status = status;
-    r.st.finish_s = t;
+    if (status != RR_OK && r.st.status == RR_OK) r.st.status = status;
+    if (--r.parts_left == 0) {
+      r.st.done = 1;
+      r.st.finish_s = t;
+    }
   }
   sv->inflight_bytes -= s.bytes;
   s.reqs.clear();
@@ -98,11 +114,12 @@ void finish_slot(rr_server sv, Slot& s, rr_status status, double t) {
   s.busy = false;
 }
 
-void insert_by_arrival(rr_server sv, int64_t id) {
+// Queues the parts of request id behind every part that arrived no later.
+void insert_by_arrival(rr_server sv, int64_t id, const std::vector<Part>& parts) {
   const double a = sv->reqs[id].st.arrival_s;
   auto it = sv->pending.end();
-  while (it != sv->pending.begin() && sv->reqs[*(it - 1)].st.arrival_s > a) --it;
-  sv->pending.insert(it, id);
+  while (it != sv->pending.begin() && sv->reqs[(it - 1)->id].st.arrival_s > a) --it;
+  sv->pending.insert(it, parts.begin(), parts.end());
 }
 
 void run_loop(rr_server sv) {
@@ -135,17 +152,18 @@ void run_loop(rr_server sv) {
       uint32_t flags = 0;
       segs.clear();
       while (!sv->pending.empty() && (int32_t)segs.size() < sv->cfg.max_batch_requests) {
-        Req& r = sv->reqs[sv->pending.front()];
+        const Part pt = sv->pending.front();
+        Req& r = sv->reqs[pt.id];
         if (r.st.arrival_s > t) break;  // not yet arrived
-        if (rays + r.st.n > sv->cfg.max_batch_rays) break;
+        if (rays + pt.n > sv->cfg.max_batch_rays) break;
         // one hit order per batch: a request asking for the other order
         // starts the next batch
         if (!segs.empty() && r.flags != flags) break;
         flags = r.flags;
-        segs.push_back(rr_segment{r.rays, r.hits, nullptr, r.st.n, r.key});
-        s.reqs.push_back(r.st.id);
-        s.bytes += r.bytes;
-        rays += r.st.n;
+        segs.push_back(rr_segment{r.rays + pt.off, r.hits + pt.off, nullptr, pt.n, r.key});
+        s.reqs.push_back(pt.id);
+        s.bytes += pt.bytes;
+        rays += pt.n;
         sv->pending.pop_front();
       }
       if (segs.empty()) continue;
@@ -154,7 +172,7 @@ void run_loop(rr_server sv) {
       const double ts = now_s(sv);
       for (int64_t id : s.reqs) {
         Req& r = sv->reqs[id];
-        r.st.start_s = ts;
+        if (r.st.start_s < 0) r.st.start_s = ts;  // the first part's launch
         r.st.batch_requests = (int32_t)segs.size();
       }
       sv->inflight_bytes += s.bytes;
@@ -175,7 +193,7 @@ void run_loop(rr_server sv) {
       std::this_thread::sleep_for(std::chrono::microseconds(20));
       lk.lock();
     } else if (!sv->pending.empty()) {
-      const double next = sv->reqs[sv->pending.front()].st.arrival_s;
+      const double next = sv->reqs[sv->pending.front().id].st.arrival_s;
       const double wait = std::max(0.0, next - now_s(sv));
       sv->cv.wait_for(lk, std::chrono::duration<double>(std::min(wait, 0.05)));
     } else {
@@ -202,7 +220,7 @@ rr_status rr_server_create(rr_scene s, const rr_server_config* cfg, rr_server* o
   *out = nullptr;
   if (!s || !cfg || cfg->slots < 1 || cfg->slots > 16 || cfg->max_batch_rays <= 0 ||
       cfg->max_batch_rays >= RR_MAX_RAYS || cfg->max_batch_requests < 1 || cfg->max_batch_requests > 4096 ||
-      cfg->hbm_budget_bytes <= 0)
+      cfg->hbm_budget_bytes <= 0 || cfg->split_rays < 0)
     return RR_ERR_INVALID_ARGUMENT;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != s->d.device) return RR_ERR_INVALID_ARGUMENT;
@@ -282,13 +300,23 @@ rr_status rr_server_submit(rr_server sv, const rr_ray* rays, int64_t n, const rr
   r.st.id = sv->next_id++;
   r.st.n = n;
   r.st.arrival_s = arrival_s >= 0 ? arrival_s : now_s(sv);
+  r.st.start_s = -1.0;
   r.rays = rays;
   r.hits = hits;
   r.key = *key;
   r.flags = flags;
-  r.bytes = (int64_t)(sv->bytes_per_ray * (double)n);
+  // parts: only a request in ray order is split (its hits do not depend on
+  // the split); an empty request is one empty part
+  const int64_t split = sv->cfg.split_rays;
+  const int64_t part = (flags & RR_HITS_ORIGINAL_ORDER) && split > 0 && n > split ? split : std::max<int64_t>(n, 1);
+  std::vector<Part> parts;
+  for (int64_t off = 0; off == 0 || off < n; off += part) {
+    const int64_t m = std::min(part, n - off);
+    parts.push_back(Part{r.st.id, off, m, (int64_t)(sv->bytes_per_ray * (double)m)});
+  }
+  r.parts_left = (int32_t)parts.size();
   sv->reqs[r.st.id] = r;
-  insert_by_arrival(sv, r.st.id);
+  insert_by_arrival(sv, r.st.id, parts);
   *id = r.st.id;
   sv->cv.notify_all();
   return RR_OK;
@@ -382,9 +410,9 @@ rr_status rr_server_destroy(rr_server sv) {
   {
     // requests never launched end as failed, so no waiter is left behind
     std::lock_guard<std::mutex> lk(sv->mu);
-    for (int64_t id : sv->pending) {
-      sv->reqs[id].st.done = 1;
-      sv->reqs[id].st.status = RR_ERR_DEVICE;
+    for (const Part& pt : sv->pending) {
+      sv->reqs[pt.id].st.done = 1;
+      sv->reqs[pt.id].st.status = RR_ERR_DEVICE;
     }
     sv->pending.clear();
   }

@@ -375,3 +375,32 @@ def test_server_destroy_releases_waiting_threads(rr, city):
         t.join(10.0)
     assert all(not t.is_alive() for t in th)
     assert sorted(out) == sorted(ids) and all(v != "ok" for v in out.values())
+
+
+def test_server_splits_large_requests(rr, city):
+    """With a split size, requests in ray order larger than it are served as
+    parts (several batches, possibly on several slots at once); requests in
+    key order are not split.  Every request's hits equal the request traced
+    alone."""
+    w, scene = city
+    rng = np.random.default_rng(53)
+    sizes = [int(x) for x in np.exp(rng.uniform(np.log(200), np.log(40000), 20))] + [39999, 12001, 5000, 5001]
+    segs = make_segments(rr, w, scene, sizes, seed=53)
+    with rr.Server(scene, slots=3, hbm_budget_bytes=8 << 30, max_batch_rays=60000, max_batch_requests=4,
+                   split_rays=5000) as sv:
+        sv.start()
+        ids = [sv.submit(s["rays"], s["hits"], s["key"], arrival_s=0.0002 * k,
+                         flags=0 if k % 5 == 4 else rr.RR_HITS_ORIGINAL_ORDER) for k, s in enumerate(segs)]
+        sv.drain(120.0)
+        st = [sv.wait(i) for i in ids]
+        stats = sv.stats()
+    assert all(x["status"] == 0 and x["done"] for x in st)
+    assert stats["completed"] == len(segs) and stats["rays"] == sum(sizes)
+    # parts of 5000 rays, at most 4 per batch: more batches than requests
+    assert stats["batches"] >= sum(-(-n // 5000) if k % 5 != 4 else 1 for k, n in enumerate(sizes)) // 4
+    for k, s in enumerate(segs):
+        hits, perm = expected(rr, scene, s)
+        want = hits[perm] if k % 5 == 4 else hits
+        assert rr.hits_to_numpy(s["hits"]).tobytes() == want.tobytes(), k
+    for x in st:
+        assert x["finish_s"] >= x["start_s"] >= x["arrival_s"] - 1e-6
