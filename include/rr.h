@@ -221,10 +221,11 @@ rr_status rr_coherence_m64(const rr_ray* rays, const rr_hit* hits, int64_t n, co
  * Section 3.2: stable ascending radix sort of (key, index) pairs, in place.
  * The result is unique: the lexicographic order of (key, index) when the
  * input indices ascend (in general: by key, equal keys in input position
- * order).  For 64-bit keys below 2^27 pairs rr_sort runs a most-significant-
- * digit sort (two stable scatter passes on the two highest 8-bit digits in
- * which the keys differ, then every bucket of equal top digits sorted on its
- * other digits in LDS); otherwise an LSD sort with 8-bit digits.  n_max is the capacity; when count_dev
+ * order).  For 64-bit keys with n_max from 1,572,864 up to 2^27 rr_sort runs
+ * a most-significant-digit sort (two stable scatter passes on the two highest
+ * 8-bit digits in which the keys differ, then every bucket of equal top digits
+ * sorted on its other digits in LDS); otherwise an LSD sort with 8-bit digits
+ * (the faster one outside that range).  n_max is the capacity; when count_dev
  * (device uint32) is given, only its first *count_dev pairs are sorted
  * (count_dev must not exceed n_max).  workspace (device, >= the size
  * reported by rr_sort_workspace_size, 256-byte aligned) is scratch that the

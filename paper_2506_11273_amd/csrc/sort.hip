@@ -1310,7 +1310,12 @@ SegLayout msd_layout(int64_t n_max, uint32_t key_bits, uint32_t kpt) {
   return L;
 }
 
-bool msd_preferred(int64_t n_max, uint32_t key_bits) { return key_bits == 64 && n_max < (int64_t(1) << 27); }
+// Below about 1.5M pairs the bucket kernel runs on few CUs and its chain of
+// LDS passes takes longer than the LSD sort's passes; from 2^27 pairs on,
+// the buckets average over 2K keys.
+bool msd_preferred(int64_t n_max, uint32_t key_bits) {
+  return key_bits == 64 && n_max >= kMsdMinKeys && n_max < (int64_t(1) << 27);
+}
 
 SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_t db, uint32_t kpt) {
   SegLayout L{};

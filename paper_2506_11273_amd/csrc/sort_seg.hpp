@@ -44,7 +44,9 @@ SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_
 // kpt keys per thread in its two scatter passes).
 SegLayout msd_layout(int64_t n_max, uint32_t key_bits, uint32_t kpt);
 // Whether rr_sort and the fused call take the most-significant-digit sort
-// for a capacity of n_max keys of key_bits bits (else the LSD sort).
+// for a capacity of n_max keys of key_bits bits (else the LSD sort): 64-bit
+// keys, kMsdMinKeys <= n_max < 2^27.
+constexpr int64_t kMsdMinKeys = 3 << 19;  // 1,572,864
 bool msd_preferred(int64_t n_max, uint32_t key_bits);
 
 // Sorts every segment described by the device header and segment table
