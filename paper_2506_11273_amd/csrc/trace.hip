@@ -31,6 +31,13 @@
 // from its packets whenever at least `refill` lanes are idle, so lanes whose
 // rays finish early do not idle until the wave's longest ray ends, and the
 // rays in flight on an XCD stay a window of neighbouring slots.
+// A wave alternates between an inner-node loop and a leaf loop (while-while
+// traversal, a found leaf postponed while the lane goes on with inner nodes).
+// Neither loop runs until its last lane is done: the inner loop ends once at
+// most kLoopExit lanes still need an inner node to find a leaf, the leaf
+// loop once at most kLoopExit lanes still hold a leaf; those lanes carry
+// their state into the wave's next round, so the few long traversals of a
+// wave do not keep the other 60 lanes idle.
 // The traversal stack holds at most 3 entries per tree level; its first
 // kLdsStack entries live in LDS (interleaved by lane), the rest in scratch.
 #include <algorithm>
@@ -47,6 +54,7 @@ constexpr float kTinyDir = 1e-20f;
 constexpr int kLdsStack = 16;
 constexpr int kSpillStack = kTraceStack4 - kLdsStack;
 constexpr uint32_t kPacket = 64;  // consecutive ray slots a wave takes in turn
+constexpr int kLoopExit = 8;      // lanes left in a loop when the wave moves on
 
 __device__ __forceinline__ uint32_t read_count(const uint32_t* count_dev, uint32_t n_max) {
   if (!count_dev) return n_max;
@@ -240,7 +248,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
     };
     if (slot < 0) continue;
 
-    // ---- inner nodes, until every lane of the wave holds a postponed leaf
+    // ---- inner nodes, until all but kLoopExit lanes hold a postponed leaf
     // (or has finished), so that node tests and triangle tests do not
     // diverge within one iteration
     while (node >= 0 && node != kEmptyChild) {
@@ -319,7 +327,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
         leaf = node;
         node = pop_or_none();
       }
-      if (!__ballot(leaf == 0 && node >= 0 && node != kEmptyChild)) break;
+      if (__popcll(__ballot(leaf == 0 && node >= 0 && node != kEmptyChild)) <= kLoopExit) break;
     }
     if (node < 0 && leaf == 0) {
       leaf = node;
@@ -376,8 +384,10 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
         leaf = node;
         node = pop_or_none();
       }
+      if (__popcll(__ballot(leaf < 0)) <= kLoopExit) break;
     }
-    if (node == kEmptyChild) {
+    // a lane is done when its stack is empty and no leaf is left to test
+    if (node == kEmptyChild && leaf == 0) {
       hits[slot] = make_float4(bprim >= 0 ? tbest : __int_as_float(0x7f800000), __int_as_float(bprim), bu, bv);
       slot = -1;
     }
