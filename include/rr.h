@@ -221,7 +221,7 @@ rr_status rr_coherence_m64(const rr_ray* rays, const rr_hit* hits, int64_t n, co
  * Section 3.2: stable ascending radix sort of (key, index) pairs, in place.
  * The result is unique: the lexicographic order of (key, index) when the
  * input indices ascend (in general: by key, equal keys in input position
- * order).  For 64-bit keys with n_max from 1,572,864 up to 2^27 rr_sort runs
+ * order).  For 64-bit keys with n_max from 12,582,912 up to 2^27 rr_sort runs
  * a most-significant-digit sort (two stable scatter passes on the two highest
  * 8-bit digits in which the keys differ, then every bucket of equal top digits
  * sorted on its other digits in LDS); otherwise an LSD sort with 8-bit digits
@@ -236,6 +236,11 @@ rr_status rr_coherence_m64(const rr_ray* rays, const rr_hit* hits, int64_t n, co
 rr_status rr_sort_workspace_size(int64_t n_max, uint32_t key_bits, size_t* bytes);
 rr_status rr_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                   void* workspace, size_t ws_bytes, void* stream);
+/* The most-significant-digit sort at any size it supports: 64-bit keys with
+ * n_max below 2^27 (otherwise RR_ERR_UNSUPPORTED).  Arguments, workspace and
+ * result as for rr_sort. */
+rr_status rr_sort_msd(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                      void* workspace, size_t ws_bytes, void* stream);
 /* The LSD sort with an explicit radix digit width (4 or 8 bits) and keys
  * per thread (tile size); every choice gives the identical result, that of
  * rr_sort.  rr_sort's LSD sort and scatter passes use 8-bit digits and 8 keys
@@ -335,6 +340,11 @@ rr_status rr_trace_profile(rr_scene s, const rr_ray* rays, int64_t n, rr_hit* hi
  * (RR_ERR_INVALID_ARGUMENT) with RR_KEY_TWO_POINT_ADAPTIVE, whose table
  * learns from closest hits. */
 #define RR_ANY_HIT 32u
+/* The device-wide sort is the most-significant-digit sort (rr_sort_msd)
+ * whatever the size: 64-bit keys and n below 2^27 (otherwise
+ * RR_ERR_UNSUPPORTED); not with RR_LOCAL_SORT_* (RR_ERR_INVALID_ARGUMENT);
+ * no effect with RR_KEY_NONE. */
+#define RR_SORT_MSD 64u
 rr_status rr_reorder_workspace_size(int64_t n_max, const rr_key_params* p, size_t* bytes);
 rr_status rr_reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const uint8_t* alive,
                                const rr_key_params* p, rr_hit* hits, uint32_t* perm_out, uint32_t* count_out,

@@ -13,7 +13,7 @@ from .rr import (  # noqa: F401
     RR_KEY_NONE, RR_KEY_ORIGIN_DIRECTION, RR_KEY_ORIGIN_TERMINATION, RR_KEY_ORIGIN, RR_KEY_DIRECTION_ORIGIN,
     RR_KEY_AILA, RR_KEY_AILA_COMPACT, RR_KEY_OCTAHEDRON, RR_KEY_TWO_POINT_ADAPTIVE, RR_KEY_TWO_POINT_REAL,
     RR_LENGTH_CELLS, RR_HITS_ORIGINAL_ORDER, RR_INDIRECT, RR_LOCAL_SORT_1024, RR_LOCAL_SORT_2048,
-    RR_LOCAL_SORT_4096, RR_ANY_HIT, LengthTable,
+    RR_LOCAL_SORT_4096, RR_ANY_HIT, RR_SORT_MSD, LengthTable,
     coherence_m64, hits_to_numpy, key_params, keys_workspace_size, load, reorder_workspace_size, sort_workspace_size,
     rr_compute_keys, rr_sort, rr_local_sort, rr_gather, rr_scatter_hits, rr_trace, rr_trace_any, rr_trace_profile, rr_reorder_and_trace, rr_reorder_and_trace_noalloc,
     workspace,

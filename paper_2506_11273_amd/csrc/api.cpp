@@ -254,6 +254,18 @@ rr_status rr_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* coun
   return launch_sort_auto(keys, idx, n_max, count_dev, key_bits, workspace, ws_bytes, S(stream));
 }
 
+rr_status rr_sort_msd(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
+                      void* workspace, size_t ws_bytes, void* stream) {
+  if (!valid_n(n_max) || (key_bits != 32 && key_bits != 64)) return RR_ERR_INVALID_ARGUMENT;
+  if (n_max == 0) return RR_OK;
+  if (!msd_supported(n_max, key_bits)) return RR_ERR_UNSUPPORTED;
+  if (!is_device_ptr(keys) || !is_device_ptr(idx) || !is_device_ptr(workspace)) return RR_ERR_INVALID_ARGUMENT;
+  if (!aligned(keys, key_bits / 8) || !aligned(idx, 4) || !aligned(workspace, 256)) return RR_ERR_INVALID_ARGUMENT;
+  if (count_dev && !is_device_ptr(count_dev)) return RR_ERR_INVALID_ARGUMENT;
+  if (ws_bytes < sort_workspace_bytes_any(n_max, key_bits)) return RR_ERR_WORKSPACE_TOO_SMALL;
+  return launch_sort_auto(keys, idx, n_max, count_dev, key_bits, workspace, ws_bytes, S(stream), true);
+}
+
 rr_status rr_local_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                         uint32_t block, void* stream) {
   if (!valid_n(n_max) || (key_bits != 32 && key_bits != 64)) return RR_ERR_INVALID_ARGUMENT;
@@ -367,7 +379,8 @@ rr_status reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const uin
                             uint32_t flags, void* workspace, size_t ws_bytes, void* stream, bool ws_is_scratch) {
   if (!s || !p || !valid_n(n)) return RR_ERR_INVALID_ARGUMENT;
   constexpr uint32_t kLocal = RR_LOCAL_SORT_1024 | RR_LOCAL_SORT_2048 | RR_LOCAL_SORT_4096;
-  if (flags & ~(RR_HITS_ORIGINAL_ORDER | RR_INDIRECT | RR_ANY_HIT | kLocal)) return RR_ERR_INVALID_ARGUMENT;
+  if (flags & ~(RR_HITS_ORIGINAL_ORDER | RR_INDIRECT | RR_ANY_HIT | RR_SORT_MSD | kLocal))
+    return RR_ERR_INVALID_ARGUMENT;
   const bool any = (flags & RR_ANY_HIT) != 0;
   const uint32_t local = flags & kLocal;
   if (local & (local - 1)) return RR_ERR_INVALID_ARGUMENT;  // at most one block size
@@ -376,6 +389,8 @@ rr_status reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const uin
                                : local == RR_LOCAL_SORT_4096 ? 4096u
                                                              : 0u;
   const bool sorted = p->kind != RR_KEY_NONE;
+  const bool force_msd = sorted && (flags & RR_SORT_MSD) != 0;
+  if (force_msd && local_block) return RR_ERR_INVALID_ARGUMENT;
   KeyPlan plan{};
   if (sorted) {
     rr_status st = make_key_plan(p, &plan);
@@ -393,6 +408,7 @@ rr_status reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const uin
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != s->d.device) return RR_ERR_INVALID_ARGUMENT;
   const uint32_t kb = sorted ? p->key_bits : 32u;
+  if (force_msd && !msd_supported(n, kb)) return RR_ERR_UNSUPPORTED;
   const ReorderLayout L = reorder_layout(n, kb);
   if (!workspace || (!ws_is_scratch && !is_device_ptr(workspace)) || !aligned(workspace, 256))
     return RR_ERR_INVALID_ARGUMENT;
@@ -423,7 +439,7 @@ rr_status reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const uin
     // dense device-wide sort: the keys kernel also counts the digits, and
     // the sort's last pass gathers the rays
     if ((r = launch_keys_sort_gather(rays, n, plan, keys, idx, sort_default_kpt(n), w + L.sortws, L.sort_bytes, srays,
-                                     st)) != RR_OK)
+                                     st, force_msd)) != RR_OK)
       return r;
     gathered = true;
   } else if (sorted) {
@@ -433,10 +449,10 @@ rr_status reorder_and_trace(rr_scene s, const rr_ray* rays, int64_t n, const uin
     } else if (!indirect) {
       // the device-wide sort's last pass also gathers the rays
       if ((r = launch_sort_gather(keys, idx, n, cnt, kb, 8, sort_default_kpt(n), w + L.sortws, L.sort_bytes, rays, srays,
-                                  st)) != RR_OK)
+                                  st, force_msd)) != RR_OK)
         return r;
       gathered = true;
-    } else if ((r = launch_sort_auto(keys, idx, n, cnt, kb, w + L.sortws, L.sort_bytes, st)) != RR_OK) {
+    } else if ((r = launch_sort_auto(keys, idx, n, cnt, kb, w + L.sortws, L.sort_bytes, st, force_msd)) != RR_OK) {
       return r;
     }
   } else {

@@ -468,7 +468,7 @@ __device__ uint32_t look_back(const uint32_t* status, const uint32_t* gstatus, c
   return acc;
 }
 
-template <typename K, int DB, int KPT>
+template <typename K, int DB, int KPT, int MODE = 0>
 __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__ keys_in,
                                                            const uint32_t* __restrict__ idx_in,
                                                            K* __restrict__ keys_out, uint32_t* __restrict__ idx_out,
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
   for (uint32_t i = tid; i < kSortWaves * R; i += kSortThreads) (&sm.wave_hist[0][0])[i] = 0;
 
   uint32_t shift = shift_in, pass = pass_in, dh = 0, dl = 0;
-  if (msd.mode == 1) {
+  if constexpr (MODE == 1) {
     if (tid == 0) sm.nonuni = 0;
     __syncthreads();
     const uint32_t n_all = hdr->total_keys;
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
     dl = below ? 31u - (uint32_t)__builtin_clz(below) : (dh > 0 ? dh - 1 : 1u);
     shift = dh * DB;
     pass = dh;
-  } else if (msd.mode == 2) {
+  } else if constexpr (MODE == 2) {
     shift = msd.plan->dl * DB;
   }
 
@@ -581,8 +581,10 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
         for (uint32_t c = 0; c < copies; ++c) h += hist[(((size_t)s * copies + c) * passes + pass) * R + tid];
       const uint32_t ex = block_scan(h, sm.scan, &total);
       if (tid < R) sm.base[tid] = sg.off + ex;
-      if (msd.mode == 2 && lt == 0 && tid < R) msd.bstart[(size_t)s * R + tid] = sg.off + ex;
-      if (msd.mode == 1) {
+      if constexpr (MODE == 2) {
+        if (lt == 0 && tid < R) msd.bstart[(size_t)s * R + tid] = sg.off + ex;
+      }
+      if constexpr (MODE == 1) {
         // the segments of the second pass: one per value of digit dh
         const uint32_t nt = tid < R ? (h + kTile - 1) / kTile : 0u;
         uint32_t ttot;
@@ -1101,8 +1103,9 @@ struct Resident {
     static const uint32_t v = resident(k_seg_hist<K, DB, KPT>, kSortThreads);
     return v;
   }
+  template <int MODE = 0>
   static uint32_t pass() {
-    static const uint32_t v = resident(k_seg_pass<K, DB, KPT>, kSortThreads);
+    static const uint32_t v = resident(k_seg_pass<K, DB, KPT, MODE>, kSortThreads);
     return v;
   }
 };
@@ -1230,7 +1233,6 @@ rr_status msd_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, co
   uint32_t* gstatus2 = reinterpret_cast<uint32_t*>(ws + L.gstatus2);
 
   const uint32_t hist_res = Resident<K, 8, KPT>::hist();
-  const uint32_t pass_res = Resident<K, 8, KPT>::pass();
   const uint32_t hist_words = L.hist_copies * L.passes * R;
   hipLaunchKernelGGL(k_msd_setup, dim3(64), dim3(256), 0, st, count_dev, n_max, L.tile, hdr, segs, hist, hist_words,
                      hist2, R * R, hdr2, plan);
@@ -1249,7 +1251,8 @@ rr_status msd_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, co
                        L.status2_stride, gstatus2, L.gstatus2_stride, (const MsdPlan*)nullptr, 2u, R, R + 1);
   }
   // first pass: by dh, into the alternate buffers
-  hipLaunchKernelGGL((k_seg_pass<K, 8, KPT>), dim3(std::max(1u, std::min(L.max_tiles, pass_res))),
+  hipLaunchKernelGGL((k_seg_pass<K, 8, KPT, 1>),
+                     dim3(std::max(1u, std::min(L.max_tiles, Resident<K, 8, KPT>::template pass<1>()))),
                      dim3(kSortThreads), 0, st, keys, idx, kalt, ialt, hdr, segs, 0u, L.passes, 0u, L.hist_copies, hist,
                      status2, gstatus2, (uint32_t*)nullptr, (const float4*)nullptr, (float4*)nullptr, 0u,
                      MsdArgs{1u, plan, hdr2, segs2, bstart});
@@ -1259,7 +1262,8 @@ rr_status msd_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, co
                      dim3(kSortThreads), 0, st, kalt, hdr2, segs2, 1u, 1u, hist2, (uint32_t*)nullptr, 0u,
                      (uint32_t*)nullptr, 0u, (const MsdPlan*)plan, 0u, 0u, 0u);
   // second pass: by dl within each dh segment, back into the caller's buffers
-  hipLaunchKernelGGL((k_seg_pass<K, 8, KPT>), dim3(std::max(1u, std::min(L.max_tiles + R, pass_res))),
+  hipLaunchKernelGGL((k_seg_pass<K, 8, KPT, 2>),
+                     dim3(std::max(1u, std::min(L.max_tiles + R, Resident<K, 8, KPT>::template pass<2>()))),
                      dim3(kSortThreads), 0, st, kalt, ialt, keys, idx, hdr2, segs2, 0u, 1u, 0u, 1u, hist2,
                      status2 + L.status2_stride, gstatus2 + L.gstatus2_stride, (uint32_t*)nullptr,
                      (const float4*)nullptr, (float4*)nullptr, 0u, MsdArgs{2u, plan, nullptr, nullptr, bstart});
@@ -1310,11 +1314,16 @@ SegLayout msd_layout(int64_t n_max, uint32_t key_bits, uint32_t kpt) {
   return L;
 }
 
-// Below about 1.5M pairs the bucket kernel runs on few CUs and its chain of
-// LDS passes takes longer than the LSD sort's passes; from 2^27 pairs on,
-// the buckets average over 2K keys.
+// From 2^27 pairs on the buckets average over 2K keys.  Below about 12M
+// pairs the LSD sort is as fast or faster: its eight scatter passes are
+// short, while the bucket kernel's chains of in-LDS passes run on fewer
+// blocks than there are CUs' worth of work to hide them.
+bool msd_supported(int64_t n_max, uint32_t key_bits) {
+  return key_bits == 64 && n_max > 0 && n_max < (int64_t(1) << 27);
+}
+
 bool msd_preferred(int64_t n_max, uint32_t key_bits) {
-  return key_bits == 64 && n_max >= kMsdMinKeys && n_max < (int64_t(1) << 27);
+  return msd_supported(n_max, key_bits) && n_max >= kMsdMinKeys;
 }
 
 SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_t db, uint32_t kpt) {
@@ -1360,7 +1369,7 @@ size_t sort_workspace_bytes_any(int64_t n_max, uint32_t key_bits) {
   size_t m = 0;
   for (uint32_t db : {4u, 8u})
     for (uint32_t kpt : {8u, 16u}) m = std::max(m, sort_workspace_bytes(n_max, key_bits, db, kpt));
-  if (msd_preferred(n_max, key_bits)) m = std::max(m, msd_layout(n_max, key_bits, sort_default_kpt(n_max)).total);
+  if (msd_supported(n_max, key_bits)) m = std::max(m, msd_layout(n_max, key_bits, sort_default_kpt(n_max)).total);
   return m;
 }
 
@@ -1369,6 +1378,10 @@ void sort_warm(uint32_t key_bits, uint32_t db, uint32_t kpt) {
   if (sizeof(KT) * 8 == key_bits && db == DBV && kpt == KPTV) {      \
     (void)Resident<KT, DBV, KPTV>::hist();                           \
     (void)Resident<KT, DBV, KPTV>::pass();                           \
+    if (sizeof(KT) == 8 && DBV == 8) {                               \
+      (void)Resident<KT, DBV, KPTV>::template pass<1>();             \
+      (void)Resident<KT, DBV, KPTV>::template pass<2>();             \
+    }                                                                \
   }
   RR_WARM_CASE(uint32_t, 8, 16)
   RR_WARM_CASE(uint32_t, 8, 8)
@@ -1428,10 +1441,11 @@ rr_status launch_msd(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* c
 }  // namespace
 
 rr_status launch_sort_auto(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
-                           void* ws, size_t ws_bytes, hipStream_t st) {
+                           void* ws, size_t ws_bytes, hipStream_t st, bool force_msd) {
   if (key_bits != 32 && key_bits != 64) return RR_ERR_UNSUPPORTED;
+  if (force_msd && !msd_supported(n_max, key_bits)) return RR_ERR_UNSUPPORTED;
   const uint32_t kpt = sort_default_kpt(n_max);
-  if (msd_preferred(n_max, key_bits))
+  if (force_msd || msd_preferred(n_max, key_bits))
     return launch_msd(keys, idx, n_max, count_dev, key_bits, kpt, ws, ws_bytes, nullptr, nullptr, 0u, st, nullptr);
   return launch_sort(keys, idx, n_max, count_dev, key_bits, 8, kpt, ws, ws_bytes, st);
 }
@@ -1446,13 +1460,15 @@ rr_status launch_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* 
 }
 
 rr_status launch_keys_sort_gather(const rr_ray* rays, int64_t n, const KeyPlan& plan, void* keys, uint32_t* idx,
-                                  uint32_t kpt, void* ws, size_t ws_bytes, rr_ray* rays_out, hipStream_t st) {
+                                  uint32_t kpt, void* ws, size_t ws_bytes, rr_ray* rays_out, hipStream_t st,
+                                  bool force_msd) {
   const uint32_t key_bits = plan.key64 ? 64u : 32u;
   if (n <= 0) return RR_OK;
   if (!sort_config_supported(key_bits, 8, kpt) || (plan.key64 && key_family(plan.kind) == 3))
     return RR_ERR_UNSUPPORTED;
+  if (force_msd && !msd_supported(n, key_bits)) return RR_ERR_UNSUPPORTED;
   const KeySource src{rays, plan};
-  if (msd_preferred(n, key_bits))
+  if (force_msd || msd_preferred(n, key_bits))
     return launch_msd(keys, idx, n, nullptr, key_bits, kpt, ws, ws_bytes, rays, rays_out, (uint32_t)n, st, &src);
   const SegLayout L = seg_layout(n, 1, key_bits, 8, kpt);
   if (ws_bytes < L.total) return RR_ERR_WORKSPACE_TOO_SMALL;
@@ -1471,9 +1487,10 @@ rr_status launch_keys_sort_gather(const rr_ray* rays, int64_t n, const KeyPlan& 
 
 rr_status launch_sort_gather(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                              uint32_t db, uint32_t kpt, void* ws, size_t ws_bytes, const rr_ray* rays_in,
-                             rr_ray* rays_out, hipStream_t st) {
+                             rr_ray* rays_out, hipStream_t st, bool force_msd) {
   if (!sort_config_supported(key_bits, db, kpt)) return RR_ERR_UNSUPPORTED;
-  if (db == 8 && msd_preferred(n_max, key_bits))
+  if (force_msd && (db != 8 || !msd_supported(n_max, key_bits))) return RR_ERR_UNSUPPORTED;
+  if (db == 8 && (force_msd || msd_preferred(n_max, key_bits)))
     return launch_msd(keys, idx, n_max, count_dev, key_bits, kpt, ws, ws_bytes, rays_in, rays_out, (uint32_t)n_max, st,
                       nullptr);
   const SegLayout L = seg_layout(n_max, 1, key_bits, db, kpt);

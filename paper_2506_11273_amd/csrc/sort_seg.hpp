@@ -43,10 +43,11 @@ SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_
 // Layout of the single-segment most-significant-digit sort (8-bit digits,
 // kpt keys per thread in its two scatter passes).
 SegLayout msd_layout(int64_t n_max, uint32_t key_bits, uint32_t kpt);
-// Whether rr_sort and the fused call take the most-significant-digit sort
-// for a capacity of n_max keys of key_bits bits (else the LSD sort): 64-bit
-// keys, kMsdMinKeys <= n_max < 2^27.
-constexpr int64_t kMsdMinKeys = 3 << 19;  // 1,572,864
+// The most-significant-digit sort exists for 64-bit keys below 2^27
+// (msd_supported); rr_sort and the fused call take it by themselves from
+// kMsdMinKeys keys on (msd_preferred), else the LSD sort.
+constexpr int64_t kMsdMinKeys = 3 << 22;  // 12,582,912
+bool msd_supported(int64_t n_max, uint32_t key_bits);
 bool msd_preferred(int64_t n_max, uint32_t key_bits);
 
 // Sorts every segment described by the device header and segment table
@@ -67,9 +68,11 @@ rr_status launch_seg_sort(void* keys, uint32_t* idx, const SegLayout& L, void* w
 // and kpt keys per thread, the histogram counted while the keys are
 // computed, and the rays gathered into key order by the last pass
 // (rays_out[i] = rays[idx[i]]).  keys / idx receive n entries; ws holds the
-// sort workspace of seg_layout(n, 1, key bits, 8, kpt).
+// sort workspace of seg_layout(n, 1, key bits, 8, kpt).  force_msd takes the
+// most-significant-digit sort at any supported size.
 rr_status launch_keys_sort_gather(const rr_ray* rays, int64_t n, const KeyPlan& plan, void* keys, uint32_t* idx,
-                                  uint32_t kpt, void* ws, size_t ws_bytes, rr_ray* rays_out, hipStream_t st);
+                                  uint32_t kpt, void* ws, size_t ws_bytes, rr_ray* rays_out, hipStream_t st,
+                                  bool force_msd = false);
 
 // Runs the one-time occupancy queries of a sort configuration, so that a
 // later stream capture records kernel launches only.

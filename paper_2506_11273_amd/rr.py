@@ -50,6 +50,7 @@ RR_LOCAL_SORT_1024 = 4
 RR_LOCAL_SORT_2048 = 8
 RR_LOCAL_SORT_4096 = 16
 RR_ANY_HIT = 32
+RR_SORT_MSD = 64
 
 # every symbol include/rr.h declares
 EXPORTS = (
@@ -57,7 +58,7 @@ EXPORTS = (
     "rr_scene_create", "rr_scene_create_ex", "rr_scene_bounds", "rr_scene_info", "rr_scene_destroy",
     "rr_keys_workspace_size", "rr_compute_keys", "rr_length_table_init", "rr_length_table_accumulate",
     "rr_coherence_m64",
-    "rr_sort_workspace_size", "rr_sort", "rr_sort_ex", "rr_local_sort",
+    "rr_sort_workspace_size", "rr_sort", "rr_sort_ex", "rr_sort_msd", "rr_local_sort",
     "rr_gather", "rr_scatter_hits", "rr_trace", "rr_trace_ex", "rr_trace_any", "rr_trace_profile",
     "rr_reorder_workspace_size", "rr_reorder_and_trace", "rr_reorder_and_trace_noalloc",
 )
@@ -107,6 +108,7 @@ def load():
         "rr_sort_workspace_size": ([i64, u32, P(sz)], st),
         "rr_sort": ([vp, vp, i64, vp, u32, vp, sz, vp], st),
         "rr_sort_ex": ([vp, vp, i64, vp, u32, u32, u32, vp, sz, vp], st),
+        "rr_sort_msd": ([vp, vp, i64, vp, u32, vp, sz, vp], st),
         "rr_local_sort": ([vp, vp, i64, vp, u32, u32, vp], st),
         "rr_gather": ([vp, vp, i64, vp, vp, vp], st),
         "rr_scatter_hits": ([vp, vp, i64, vp, vp, vp], st),
@@ -331,9 +333,10 @@ def rr_compute_keys(rays, params: KeyParams, alive=None, keys=None, idx=None, co
 
 
 def rr_sort(keys, idx, count=None, key_bits: Optional[int] = None, digit_bits: int = 8,
-            keys_per_thread: Optional[int] = None, ws=None, stream=None):
+            keys_per_thread: Optional[int] = None, ws=None, stream=None, msd: bool = False):
     """Stable in-place sort of (keys, idx); keys_per_thread None takes the
-    library's choice for the size (rr_sort), a value calls rr_sort_ex."""
+    library's choice for the size (rr_sort), a value calls rr_sort_ex (the
+    LSD sort), msd=True calls rr_sort_msd."""
     torch = _torch()
     L = load()
     n = int(keys.shape[0])
@@ -344,7 +347,9 @@ def rr_sort(keys, idx, count=None, key_bits: Optional[int] = None, digit_bits: i
     ip = _ptr(idx, "idx", torch.int32)
     cp = _ptr(count, "count", torch.int32, False)
     wp, wb = _ptr(ws, "workspace"), ws.numel() * ws.element_size()
-    if keys_per_thread is None and digit_bits == 8:
+    if msd:
+        _check(L.rr_sort_msd(kp, ip, n, cp, kb, wp, wb, _stream(stream)), "rr_sort_msd")
+    elif keys_per_thread is None and digit_bits == 8:
         _check(L.rr_sort(kp, ip, n, cp, kb, wp, wb, _stream(stream)), "rr_sort")
     else:
         _check(L.rr_sort_ex(kp, ip, n, cp, kb, digit_bits, keys_per_thread or 8, wp, wb, _stream(stream)),

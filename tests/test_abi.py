@@ -76,6 +76,11 @@ def test_rejects_bad_arguments_before_touching_the_device(lib):
     assert lib.rr_sort_ex(None, None, 10, None, 32, 8, 12, None, 0, None) == -4
     # empty sort is a no-op
     assert lib.rr_sort(None, None, 0, None, 32, None, 0, None) == 0
+    # the most-significant-digit sort: 64-bit keys below 2^27 only
+    assert lib.rr_sort_msd(None, None, 0, None, 64, None, 0, None) == 0
+    assert lib.rr_sort_msd(None, None, 10, None, 32, None, 0, None) == -4
+    assert lib.rr_sort_msd(None, None, 1 << 27, None, 64, None, 0, None) == -4
+    assert lib.rr_sort_msd(None, None, 10, None, 48, None, 0, None) == -1
     # scene from no triangles / non-finite vertices
     h = ctypes.c_void_p()
     assert lib.rr_scene_create(None, 0, ctypes.byref(h)) == -1

@@ -1,14 +1,15 @@
-"""GPU parity of the most-significant-digit sort that rr_sort and the fused
-call use for 64-bit keys from 1,572,864 up to 2^27 keys (the sizes here are
-in that range unless stated): two stable scatter passes on the two highest
-digits in which the keys differ, then every bucket of equal top digits
-sorted on its other digits in LDS, or, when it holds more keys than fit, by
-one block in chunks through global memory.  Its result must be the stable
-order of the oracle (Section 3.2), and the LSD sort's (rr_sort_ex) bit for
-bit, whatever the key distribution: buckets that straddle the kernel's
-windows, buckets too large for LDS with an odd or even number of differing
-digits below the top two, keys differing in one digit only, input indices
-that do not ascend, a device count below the capacity."""
+"""GPU parity of the most-significant-digit sort (rr_sort_msd, and the fused
+call with RR_SORT_MSD; rr_sort takes it by itself for 64-bit keys from
+12,582,912 keys on): two stable scatter passes on the two highest digits in
+which the keys differ, then every bucket of equal top digits sorted on its
+other digits in LDS, or, when it holds more keys than fit, by one block in
+chunks through global memory.  Its result must be the stable order of the
+oracle (Section 3.2), and the LSD sort's (rr_sort_ex) bit for bit, whatever
+the key distribution: buckets that straddle the kernel's windows, buckets
+too large for LDS with an odd or even number of differing digits below the
+top two, keys differing in one digit only, input indices that do not
+ascend, a device count below the capacity; and rr_sort on both sides of the
+size from which it takes this sort."""
 import numpy as np
 import pytest
 
@@ -20,6 +21,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 DEV = "cuda"
+THRESHOLD = 12_582_912  # 64-bit keys from this size on take the MSD sort in rr_sort
 
 
 @pytest.fixture(scope="module")
@@ -40,25 +42,25 @@ def keys_np(t, bits):
     return a.view(np.uint32) if bits == 32 else a.view(np.uint64)
 
 
-def run_both(rr, k, bits, idx_in=None, count=None):
-    """rr_sort (most-significant-digit sort) and rr_sort_ex (LSD) of the same
-    pairs; both must give the oracle's stable order by input position."""
+def run_all(rr, k, bits, idx_in=None, count=None, ways=None):
+    """The MSD sort (64-bit keys), rr_sort and the LSD sort (rr_sort_ex) of
+    the same pairs; each must give the oracle's stable order by input
+    position, so all agree bit for bit."""
     n = k.shape[0]
     idx_in = np.arange(n, dtype=np.uint32) if idx_in is None else idx_in
     m = n if count is None else count
     _, perm = O.sort_pairs(k[:m])
-    outs = []
-    for ex in (None, 8):
+    if ways is None:
+        ways = ("msd", "auto", "lsd") if bits == 64 else ("auto", "lsd")
+    for way in ways:
         kd = to_dev(k.view(np.int32 if bits == 32 else np.int64))
         idx = to_dev(idx_in.view(np.int32))
         cnt = None if count is None else torch.tensor([count], dtype=torch.int32, device=DEV)
-        rr.rr_sort(kd, idx, count=cnt, keys_per_thread=ex)
+        rr.rr_sort(kd, idx, count=cnt, key_bits=bits, msd=way == "msd", keys_per_thread=8 if way == "lsd" else None)
         gk, gi = keys_np(kd, bits), idx.cpu().numpy().view(np.uint32)
-        assert np.array_equal(gk[:m], k[:m][perm]), ("keys", ex)
-        assert np.array_equal(gi[:m], idx_in[:m][perm]), ("idx", ex)
-        assert np.array_equal(gk[m:], k[m:]) and np.array_equal(gi[m:], idx_in[m:]), ("tail", ex)
-        outs.append(gi.copy())
-    assert np.array_equal(outs[0], outs[1])
+        assert np.array_equal(gk[:m], k[:m][perm]), ("keys", way)
+        assert np.array_equal(gi[:m], idx_in[:m][perm]), ("idx", way)
+        assert np.array_equal(gk[m:], k[m:]) and np.array_equal(gi[m:], idx_in[m:]), ("tail", way)
 
 
 def big_bucket_keys(n, bits, low_bits, frac, seed):
@@ -74,82 +76,112 @@ def big_bucket_keys(n, bits, low_bits, frac, seed):
     return k.astype(np.uint32 if bits == 32 else np.uint64)
 
 
-@pytest.mark.parametrize("bits,low_bits", [(64, 24), (64, 16), (64, 40), (32, 16)])
-def test_buckets_larger_than_a_batch(rr, bits, low_bits):
-    """One bucket of ~960K keys (an odd and an even number of differing
-    digits below the top two), with reversed input indices (32-bit keys: the
-    LSD sort on the same pattern)."""
-    n = 1_600_007
-    k = big_bucket_keys(n, bits, low_bits, 0.6, 7 + low_bits)
-    run_both(rr, k, bits, idx_in=np.arange(n, dtype=np.uint32)[::-1].copy())
+@pytest.mark.parametrize("low_bits", [24, 16, 40])
+def test_buckets_larger_than_a_batch(rr, low_bits):
+    """One bucket of ~180K keys (an odd and an even number of differing
+    digits below the top two), with reversed input indices."""
+    n = 300007
+    k = big_bucket_keys(n, 64, low_bits, 0.6, 7 + low_bits)
+    run_all(rr, k, 64, idx_in=np.arange(n, dtype=np.uint32)[::-1].copy())
 
 
-@pytest.mark.parametrize("bits", [32, 64])
-def test_bucket_sizes_around_the_batch(rr, bits):
+def test_bucket_sizes_around_the_batch(rr):
     """Buckets of 1 to ~12K keys (sizes spread over the whole range, some
     just above and below a batch of 8192 and straddling the kernel's 8192-key
     windows), keys differing in every digit inside a bucket, shuffled input
     indices."""
-    rng = np.random.default_rng(bits)
-    sizes = np.concatenate([rng.integers(1, 12000, 280), [8191, 8192, 8193, 1, 2, 4095, 4097]])
+    rng = np.random.default_rng(64)
+    sizes = np.concatenate([rng.integers(1, 12000, 40), [8191, 8192, 8193, 1, 2, 4095, 4097]])
     rng.shuffle(sizes)
     n = int(sizes.sum())
     prefixes = np.sort(rng.choice(1 << 16, sizes.shape[0], replace=False)).astype(np.uint64)
-    sh = np.uint64(bits - 16)
-    k = np.repeat(prefixes << sh, sizes)
-    k |= rng.integers(0, 1 << (bits - 16), n, dtype=np.uint64)
-    k = k[rng.permutation(n)].astype(np.uint32 if bits == 32 else np.uint64)
-    run_both(rr, k, bits, idx_in=rng.permutation(n).astype(np.uint32))
+    k = np.repeat(prefixes << np.uint64(48), sizes)
+    k |= rng.integers(0, 1 << 48, n, dtype=np.uint64)
+    k = k[rng.permutation(n)]
+    run_all(rr, k, 64, idx_in=rng.permutation(n).astype(np.uint32))
 
 
-@pytest.mark.parametrize("bits", [32, 64])
-@pytest.mark.parametrize("n", [1, 2, 3, 100, 8193, 65537, (3 << 19) - 1, 3 << 19, (3 << 19) + 8191, (1 << 21) + 1])
-def test_sizes_around_the_windows_and_the_threshold(rr, bits, n):
-    """Sizes on both sides of the size from which 64-bit keys take the MSD
-    sort, and ragged against its 8,192-key windows."""
-    rng = np.random.default_rng(n + bits)
-    k = rng.integers(0, (1 << bits) - 1, n, dtype=np.uint64, endpoint=True)
-    k = (k >> np.uint64(rng.integers(0, bits - 1))).astype(np.uint32 if bits == 32 else np.uint64)
-    run_both(rr, k, bits)
+@pytest.mark.parametrize("n", [1, 2, 3, 100, 8191, 8192, 8193, 16385, 65537])
+def test_small_and_window_sizes(rr, n):
+    """Sizes ragged against the bucket kernel's 8,192-key windows."""
+    rng = np.random.default_rng(n)
+    k = rng.integers(0, (1 << 64) - 1, n, dtype=np.uint64, endpoint=True)
+    k = k >> np.uint64(rng.integers(0, 63))
+    run_all(rr, k, 64)
 
 
-@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("n", [THRESHOLD - 1, THRESHOLD])
+def test_rr_sort_on_both_sides_of_the_threshold(rr, n):
+    """rr_sort just below (LSD sort) and at (MSD sort) the size from which
+    64-bit keys take the MSD sort; both give the oracle's order."""
+    rng = np.random.default_rng(n)
+    k = rng.integers(0, (1 << 64) - 1, n, dtype=np.uint64, endpoint=True) >> np.uint64(3)
+    run_all(rr, k, 64, ways=("auto",))
+
+
 @pytest.mark.parametrize("digit", [0, 1, 3])
-def test_one_or_two_differing_digits(rr, bits, digit):
+def test_one_or_two_differing_digits(rr, digit):
     """Keys that differ in one digit only, or in that digit and the top one:
     the two scatter passes alone order them."""
-    n = 1_600_003
-    rng = np.random.default_rng(digit * 3 + bits)
-    base = np.uint64(0x0123456789ABCDEF & ((1 << bits) - 1))
+    n = 200003
+    rng = np.random.default_rng(digit * 3 + 64)
+    base = np.uint64(0x0123456789ABCDEF)
     d = rng.integers(0, 256, n, dtype=np.uint64)
     k1 = (base & ~np.uint64(255 << (8 * digit))) | (d << np.uint64(8 * digit))
-    run_both(rr, k1.astype(np.uint32 if bits == 32 else np.uint64), bits)
-    top = rng.integers(0, 4, n, dtype=np.uint64) << np.uint64(bits - 8)
-    k2 = (k1 & np.uint64((1 << (bits - 8)) - 1)) | top
-    run_both(rr, k2.astype(np.uint32 if bits == 32 else np.uint64), bits)
+    run_all(rr, k1, 64)
+    top = rng.integers(0, 4, n, dtype=np.uint64) << np.uint64(56)
+    k2 = (k1 & np.uint64((1 << 56) - 1)) | top
+    run_all(rr, k2, 64)
 
 
 def test_device_count_and_big_bucket(rr):
-    n_max, n = 1_700_000, 1_600_001
+    n_max, n = 250000, 190001
     k = big_bucket_keys(n_max, 64, 20, 0.5, 3)
-    run_both(rr, k, 64, count=n)
-    run_both(rr, k, 64, count=0)
+    run_all(rr, k, 64, count=n)
+    run_all(rr, k, 64, count=0)
 
 
 def test_fused_call_with_a_bucket_larger_than_a_batch(rr):
     """Half the rays start at one point (origin-direction keys then share
     their origin bits, so one bucket holds them all and the sort's large-
-    bucket path also gathers the rays): the fused call's permutation equals
-    the oracle's and its hits match under the closest-hit rule."""
-    w = W.soup(seed=9, n_rays=1_600_000, n_tris=2048)
+    bucket path also gathers the rays): with RR_SORT_MSD the fused call's
+    permutation equals the oracle's and its hits match under the closest-hit
+    rule; without the flag (the LSD sort at this size) it gives the same."""
+    w = W.soup(seed=9, n_rays=120000, n_tris=2048)
     rays = w.rays.copy()
     rays[::2, 0:3] = np.array([0.31, 0.62, 0.47], np.float32)
     bvh = O.BVH(w.tris)
     with rr.Scene(w.tris) as sc:
         lo, hi = sc.bounds()
-        for kind, bits in ((O.KIND_OD, 32), (O.KIND_OD, 64), (O.KIND_OT, 64)):
-            p = rr.key_params(kind, bits, lo, hi, 0.25)
-            hits, perm, _ = rr.rr_reorder_and_trace(sc, to_dev(rays), p, flags=0)
-            ref = O.reorder_and_trace(bvh, rays, kind, bits, lo, hi, 0.25)
-            assert np.array_equal(perm.cpu().numpy().view(np.uint32), ref["idx"]), (kind, bits)
-            assert_hits_match(rr.hits_to_numpy(hits), ref["hits"], ref["rays"], w.tris, f"{kind}/{bits}")
+        for kind in (O.KIND_OD, O.KIND_OT):
+            p = rr.key_params(kind, 64, lo, hi, 0.25)
+            ref = O.reorder_and_trace(bvh, rays, kind, 64, lo, hi, 0.25)
+            for flags in (rr.RR_SORT_MSD, 0, rr.RR_SORT_MSD | rr.RR_HITS_ORIGINAL_ORDER):
+                hits, perm, _ = rr.rr_reorder_and_trace(sc, to_dev(rays), p, flags=flags)
+                assert np.array_equal(perm.cpu().numpy().view(np.uint32), ref["idx"]), (kind, flags)
+                h = rr.hits_to_numpy(hits)
+                if flags & rr.RR_HITS_ORIGINAL_ORDER:
+                    back = np.empty_like(h)
+                    back[ref["idx"]] = ref["hits"]
+                    assert_hits_match(h, back, rays, w.tris, f"{kind}/{flags}")
+                else:
+                    assert_hits_match(h, ref["hits"], ref["rays"], w.tris, f"{kind}/{flags}")
+
+
+def test_fused_call_msd_flag_checks(rr):
+    """RR_SORT_MSD needs 64-bit keys and refuses the local sorts."""
+    w = W.soup(seed=10, n_rays=4096, n_tris=256)
+    with rr.Scene(w.tris) as sc:
+        lo, hi = sc.bounds()
+        rays = to_dev(w.rays)
+        with pytest.raises(rr.RRError) as e:
+            rr.rr_reorder_and_trace(sc, rays, rr.key_params(O.KIND_OD, 32, lo, hi, 0.25), flags=rr.RR_SORT_MSD)
+        assert e.value.status == -4
+        with pytest.raises(rr.RRError) as e:
+            rr.rr_reorder_and_trace(sc, rays, rr.key_params(O.KIND_OD, 64, lo, hi, 0.25),
+                                    flags=rr.RR_SORT_MSD | rr.RR_LOCAL_SORT_2048)
+        assert e.value.status == -1
+        # no sort, no effect
+        h0, _, _ = rr.rr_reorder_and_trace(sc, rays, rr.key_params(O.KIND_NONE, 32, lo, hi), flags=rr.RR_SORT_MSD)
+        h1 = rr.rr_trace(sc, rays)
+        assert torch.equal(h0.view(torch.int32), h1.view(torch.int32))

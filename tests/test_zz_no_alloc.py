@@ -2,7 +2,8 @@
 library's static device array, for callers that cannot allocate) against
 rr_reorder_and_trace with a caller workspace, through the C ABI: two calls
 in a row, the second with a smaller input, other key method, compaction and
-hit order (so the second call runs on what the first left in the array);
+hit order (so the second call runs on what the first left in the array),
+then a third with the most-significant-digit sort forced;
 keys, permutation, count and hits must be identical.  A call whose workspace
 exceeds the array is refused before anything is enqueued."""
 import ctypes
@@ -79,6 +80,15 @@ def test_noalloc_equals_the_fused_call(rr):
         live = int(d2.cpu()[0])
         assert int(c2.cpu()[0]) == live == int(alive.sum().cpu())
         assert same(q2[:live], f2[:live]) and same(h2, e2)
+        # third call: the most-significant-digit sort forced (its bucket
+        # kernel and plan live in the array too)
+        m3 = 500009
+        r3 = rays[-m3:].contiguous()
+        st, h4, q4, c4 = call_noalloc(rr, scene, r3, p1, rr.RR_SORT_MSD)
+        assert st == 0, rr.load().rr_status_string(st)
+        e4, f4, d4 = call_with_workspace(rr, scene, r3, p1, rr.RR_SORT_MSD)
+        torch.cuda.synchronize()
+        assert same(q4, f4) and same(c4, d4) and same(h4, e4)
         # more rays than the array holds: refused, outputs untouched
         big = torch.zeros((3_000_000, 8), dtype=torch.float32, device=DEV)
         st, h3, q3, c3 = call_noalloc(rr, scene, big, p1, 0)
