@@ -608,8 +608,11 @@ def sorts_only(torch, rr, W, dev, args):
     """For counter runs: device-wide sorts of 64-bit pairs, warmup and steps
     alike, in this order: the headline's Two Point keys (2,073,600), random
     keys (2,073,600), random keys (8,294,400), random keys (67,108,864, more
-    than the 256 MB MALL holds).  Each sort is one setup, one histogram and
-    8 scatter launches."""
+    than the 256 MB MALL holds); each input sorted by the most-significant-
+    digit sort (rr_sort_msd: setup, histogram, two scatter passes with a
+    histogram between them, bucket kernel) and then by the LSD sort
+    (rr_sort_ex with rr_sort's tile size: setup, histogram, 8 scatter
+    passes)."""
     w = W.bounce2_1080p()
     with rr.Scene(w.tris) as sc:
         lo, hi = sc.bounds()
@@ -632,9 +635,13 @@ def sorts_only(torch, rr, W, dev, args):
     torch.cuda.synchronize()
     for _ in range(args.warmup + args.steps):
         for k0, k, idx, ws in work:
-            k.copy_(k0)
-            torch.arange(k0.shape[0], dtype=torch.int32, device=dev, out=idx)
-            rr.rr_sort(k, idx, ws=ws)
+            for msd in (True, False):
+                k.copy_(k0)
+                torch.arange(k0.shape[0], dtype=torch.int32, device=dev, out=idx)
+                if msd:
+                    rr.rr_sort(k, idx, ws=ws, msd=True)
+                else:
+                    rr.rr_sort(k, idx, ws=ws, keys_per_thread=16 if k0.shape[0] >= 1 << 24 else 8)
     torch.cuda.synchronize()
     if args.copy_calibration:
         copy_calibration(torch, dev)
