@@ -280,7 +280,10 @@ rr_status rr_scatter_hits(const rr_hit* in, const uint32_t* idx, int64_t n_max, 
  * lexicographic minimum of (t, prim) over the triangles whose test passes
  * with tmin < t < tmax, so it does not depend on ray order, BVH or launch
  * shape.  hits[i] belongs to rays[i] for i < n (n = *count_dev when
- * given). */
+ * given).  Launches of up to about 98K rays (n_max; what one resident wave
+ * of its blocks holds) on quantised nodes trace each ray with four lanes,
+ * one child or triangle per lane; larger ones with one lane per ray in
+ * persistent wavefronts.  Both give the same hits. */
 rr_status rr_trace(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t* count_dev, rr_hit* hits,
                    void* stream);
 /* Any-hit (occlusion) trace, for shadow rays (Section 4 traces two shadow
@@ -292,9 +295,10 @@ rr_status rr_trace(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t
 rr_status rr_trace_any(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t* count_dev, rr_hit* hits,
                        void* stream);
 
-/* rr_trace with an explicit lane-refill threshold (1..64): a wavefront
- * loads new rays into its idle lanes once at least `refill` lanes are idle
- * (the traversal shape the autotuner varies).  Same hits for every value. */
+/* rr_trace in persistent wavefronts of one lane per ray at any size, with
+ * an explicit lane-refill threshold (1..64): a wavefront loads new rays
+ * into its idle lanes once at least `refill` lanes are idle (the traversal
+ * shape the autotuner varies).  Same hits for every value. */
 rr_status rr_trace_ex(rr_scene s, const rr_ray* rays, int64_t n_max, const uint32_t* count_dev, rr_hit* hits,
                       uint32_t refill, void* stream);
 

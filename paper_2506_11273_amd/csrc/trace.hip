@@ -404,6 +404,235 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same trace with four lanes per ray, for launches too small to fill the
+// device: with one ray per lane such a launch leaves most SIMDs with one wave
+// or none, and its time is the latency of its longest traversals.  Here the
+// four lanes of a quad share a ray and its state; lane q tests child q of
+// each inner node (and triangles q, q + 4, ... of each leaf), so a node visit
+// takes about half the issue time.  The quad orders the children it hit by
+// entry distance (ties by child slot) with cross-lane moves inside the quad,
+// pushes the farther ones and goes on with the nearest; the traversal stack
+// lives in LDS whole.  Control flow is uniform within a quad, so every
+// cross-lane move reads active lanes.  Box and triangle tests are those of
+// k_trace4 (the same operations in the same order), so the hits are the
+// same; the any-hit variant reports the (t, id)-least occluder of the first
+// leaf that has one.
+constexpr int kQuadBlock = 256;
+constexpr int kQuadRays = kQuadBlock / 4;  // rays per block
+constexpr int kQuadExit = 2;               // quads left in a loop when the wave moves on
+
+// Cross-lane moves inside a quad (lane i reads lane i ^ m).
+__device__ __forceinline__ int32_t quad_xor1(int32_t x) { return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ int32_t quad_xor2(int32_t x) { return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false); }
+__device__ __forceinline__ int32_t quad_xor3(int32_t x) { return __builtin_amdgcn_update_dpp(0, x, 0x1B, 0xF, 0xF, false); }
+__device__ __forceinline__ float quad_xor1(float x) { return __int_as_float(quad_xor1(__float_as_int(x))); }
+__device__ __forceinline__ float quad_xor2(float x) { return __int_as_float(quad_xor2(__float_as_int(x))); }
+__device__ __forceinline__ float quad_xor3(float x) { return __int_as_float(quad_xor3(__float_as_int(x))); }
+
+// Distances to the near and far planes of one child (byte `sh / 8` of the
+// code words) along one axis: qaxis for a single child.
+__device__ __forceinline__ void qaxis1(float p, float s, float o, float inv, float ainv20, uint32_t wnear,
+                                       uint32_t wfar, uint32_t sh, float* tn, float* tf) {
+  const float delta = p - o;
+  const float step = s * inv;
+  const float ei = __builtin_fmaf(fabsf(delta), ainv20, fabsf(step) * 0x1p-12f);
+  const float di = delta * inv;
+  *tn = __builtin_fmaf((float)((wnear >> sh) & 0xFFu), step, di - ei);
+  *tf = __builtin_fmaf((float)((wfar >> sh) & 0xFFu), step, di + ei);
+}
+
+// (t, id) of lane pairs: the lexicographically smaller, with its u, v.
+__device__ __forceinline__ void quad_min(float& t, int32_t& id, float& u, float& v, float ot, int32_t oid, float ou,
+                                         float ov) {
+  const bool take = ot < t || (ot == t && oid < id);
+  t = take ? ot : t;
+  id = take ? oid : id;
+  u = take ? ou : u;
+  v = take ? ov : v;
+}
+
+template <int BLOCK, bool ANY>
+__global__ __launch_bounds__(BLOCK) void k_trace_quad(const float4* __restrict__ nodes,
+                                                      const float4* __restrict__ tris, int32_t root,
+                                                      const float4* __restrict__ rays,
+                                                      const uint32_t* __restrict__ idx, const uint32_t* count_dev,
+                                                      uint32_t n_max, float4* __restrict__ hits) {
+  constexpr int kRays = BLOCK / 4;
+  __shared__ int32_t s_stack[kTraceStack4 * kRays];
+  const uint32_t n = read_count(count_dev, n_max);
+  const uint32_t q = threadIdx.x & 3u;
+  const uint32_t rb = threadIdx.x >> 2;
+  const uint32_t slot = blockIdx.x * (uint32_t)kRays + rb;
+  if (slot >= n) return;  // whole quads leave together
+  const uint32_t quad_shift = (threadIdx.x & (kWave - 1)) & ~3u;
+  int32_t* stack = s_stack + rb;  // entry e at stack[e * kRays]
+
+  Ray R{};
+  float tbest = __int_as_float(0x7f800000), bu = 0.0f, bv = 0.0f;
+  int32_t bprim = -1;
+  int32_t node = kEmptyChild, leaf = 0;
+  int sp = 0;
+  const uint32_t r = idx ? idx[slot] : slot;
+  if (r < n_max) {
+    const float4 a = rays[2 * (size_t)r];
+    const float4 b = rays[2 * (size_t)r + 1];
+    R.ox = a.x; R.oy = a.y; R.oz = a.z; R.tmin = a.w;
+    R.dx = b.x; R.dy = b.y; R.dz = b.z; R.tmax = b.w;
+    R.ix = 1.0f / nudge(b.x);
+    R.iy = 1.0f / nudge(b.y);
+    R.iz = 1.0f / nudge(b.z);
+    R.ax = fabsf(R.ix) * 0x1p-20f;
+    R.ay = fabsf(R.iy) * 0x1p-20f;
+    R.az = fabsf(R.iz) * 0x1p-20f;
+    tbest = b.w;
+    node = root;
+  }
+  auto pop_or_none = [&]() -> int32_t {
+    if (sp == 0) return kEmptyChild;
+    --sp;
+    return stack[sp * kRays];
+  };
+  const uint32_t sh = 8u * q;
+  const float inf = __int_as_float(0x7f800000);
+
+  while (true) {
+    // ---- inner nodes, until all but kQuadExit quads hold a postponed leaf
+    while (node >= 0 && node != kEmptyChild) {
+      const float4* N = nodes + 4 * (size_t)node;
+      const float4 a = N[0], b = N[1], c = N[2];
+      const int4 cc = *reinterpret_cast<const int4*>(N + 3);
+      const int32_t child = q == 0 ? cc.x : q == 1 ? cc.y : q == 2 ? cc.z : cc.w;
+      const uint32_t xl = __float_as_uint(b.x), xh = __float_as_uint(b.y);
+      const uint32_t yl = __float_as_uint(b.z), yh = __float_as_uint(b.w);
+      const uint32_t zl = __float_as_uint(c.x), zh = __float_as_uint(c.y);
+      float nx, fx, ny, fy, nz, fz, tn;
+      qaxis1(a.x, c.z, R.ox, R.ix, R.ax, R.ix < 0.0f ? xh : xl, R.ix < 0.0f ? xl : xh, sh, &nx, &fx);
+      qaxis1(a.y, c.w, R.oy, R.iy, R.ay, R.iy < 0.0f ? yh : yl, R.iy < 0.0f ? yl : yh, sh, &ny, &fy);
+      qaxis1(a.z, a.w, R.oz, R.iz, R.az, R.iz < 0.0f ? zh : zl, R.iz < 0.0f ? zl : zh, sh, &nz, &fz);
+      const bool hit = qslab(nx, fx, ny, fy, nz, fz, R.tmin, tbest, &tn) && child != kEmptyChild;
+      // rank among the quad's hits: nearer first, ties by child slot
+      const float key = hit ? tn : inf;
+      const float k1 = quad_xor1(key), k2 = quad_xor2(key), k3 = quad_xor3(key);
+      const uint32_t q1 = q ^ 1u, q2 = q ^ 2u, q3 = q ^ 3u;
+      const int rank = (int)(k1 < key || (k1 == key && q1 < q)) + (int)(k2 < key || (k2 == key && q2 < q)) +
+                       (int)(k3 < key || (k3 == key && q3 < q));
+      const int m = (int)__popcll((__ballot(hit) >> quad_shift) & 0xFull);
+      if (m > 0) {
+        // the farther hits onto the stack, farthest deepest; the nearest is next
+        if (hit && rank >= 1) stack[(sp + m - 1 - rank) * kRays] = child;
+        sp += m - 1;
+        int32_t c0 = (hit && rank == 0) ? child : 0;
+        c0 |= quad_xor1(c0);
+        c0 |= quad_xor2(c0);
+        node = c0;
+      } else {
+        node = pop_or_none();
+      }
+      if (node < 0 && leaf == 0) {
+        leaf = node;
+        node = pop_or_none();
+      }
+      if (__popcll(__ballot(leaf == 0 && node >= 0 && node != kEmptyChild)) <= 4 * kQuadExit) break;
+    }
+    if (node < 0 && leaf == 0) {
+      leaf = node;
+      node = pop_or_none();
+    }
+
+    // ---- leaves: lane q tests triangles q, q + 4, ...; the quad keeps the least (t, id)
+    while (leaf < 0) {
+      const int32_t code = ~leaf;
+      const int32_t first = code >> 3, count = code & 7;
+      float lt = tbest, lu = bu, lv = bv;
+      int32_t lp = bprim;
+      for (int32_t k = (int32_t)q; k < count; k += 4) {
+        const float4* T = tris + 3 * (size_t)(first + k);
+        const float4 a = T[0], b = T[1], c = T[2];
+        const float e1x = a.w, e1y = b.x, e1z = b.y;
+        const float e2x = b.z, e2y = b.w, e2z = c.x;
+        const int32_t prim = __float_as_int(c.y);
+        const float sx = R.ox - a.x, sy = R.oy - a.y, sz = R.oz - a.z;
+        const float px = R.dy * e2z - R.dz * e2y;
+        const float py = R.dz * e2x - R.dx * e2z;
+        const float pz = R.dx * e2y - R.dy * e2x;
+        const float det = (e1x * px + e1y * py) + e1z * pz;
+        if (det == 0.0f) continue;
+        const float inv = 1.0f / det;
+        const float u = ((sx * px + sy * py) + sz * pz) * inv;
+        if (!(u >= 0.0f && u <= 1.0f)) continue;
+        const float qx = sy * e1z - sz * e1y;
+        const float qy = sz * e1x - sx * e1z;
+        const float qz = sx * e1y - sy * e1x;
+        const float v = ((R.dx * qx + R.dy * qy) + R.dz * qz) * inv;
+        if (!(v >= 0.0f && u + v <= 1.0f)) continue;
+        const float t = ((e2x * qx + e2y * qy) + e2z * qz) * inv;
+        if (t > R.tmin && (t < lt || (t == lt && prim < lp))) {
+          lt = t;
+          lp = prim;
+          lu = u;
+          lv = v;
+        }
+      }
+      quad_min(lt, lp, lu, lv, quad_xor1(lt), quad_xor1(lp), quad_xor1(lu), quad_xor1(lv));
+      quad_min(lt, lp, lu, lv, quad_xor2(lt), quad_xor2(lp), quad_xor2(lu), quad_xor2(lv));
+      tbest = lt;
+      bprim = lp;
+      bu = lu;
+      bv = lv;
+      leaf = 0;
+      if constexpr (ANY) {
+        if (bprim >= 0) {  // any occluder ends the ray
+          node = kEmptyChild;
+          sp = 0;
+        }
+      }
+      if (node < 0) {
+        leaf = node;
+        node = pop_or_none();
+      }
+      if (__popcll(__ballot(leaf < 0)) <= 4 * kQuadExit) break;
+    }
+    // a quad is done when its stack is empty and no leaf is left to test
+    if (node == kEmptyChild && leaf == 0) {
+      if (q == 0)
+        hits[slot] = make_float4(bprim >= 0 ? tbest : __int_as_float(0x7f800000), __int_as_float(bprim), bu, bv);
+      return;
+    }
+  }
+}
+
+// Rays of one resident wave of k_trace_quad blocks (LDS bounds it to about
+// six blocks per CU).  Launches up to this size go to k_trace_quad
+// (quantised nodes, closest and any hit): beyond it the blocks run in
+// rounds and the one-lane kernel is as fast or faster.  Larger launches and
+// every batch take k_trace4.
+int64_t quad_capacity() {
+  static const int64_t cached = [] {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace_quad<kQuadBlock, false>, kQuadBlock, 0) !=
+            hipSuccess ||
+        per <= 0)
+      per = 1;
+    return (int64_t)cus * per * kQuadRays;
+  }();
+  return cached;
+}
+
+template <bool ANY>
+rr_status launch_quad(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
+                      const uint32_t* count_dev, rr_hit* hits, hipStream_t st) {
+  const uint32_t blocks = (uint32_t)((n_max + kQuadRays - 1) / kQuadRays);
+  hipLaunchKernelGGL((k_trace_quad<kQuadBlock, ANY>), dim3(blocks), dim3(kQuadBlock), 0, st, s.nodes, s.tris, s.root,
+                     reinterpret_cast<const float4*>(rays), idx, count_dev, (uint32_t)n_max,
+                     reinterpret_cast<float4*>(hits));
+  RR_LAUNCH_CHECK();
+  return RR_OK;
+}
+
 constexpr int kTraceBlock = 256;
 
 // Blocks of one resident wave of the grid, queried once per instance (a
@@ -460,6 +689,9 @@ rr_status launch4(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx,
 
 rr_status launch_trace(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
                        const uint32_t* count_dev, rr_hit* hits, hipStream_t st) {
+  if (n_max <= 0) return RR_OK;
+  if (s.quantised && n_max <= quad_capacity())
+    return launch_quad<false>(s, rays, idx, n_max, count_dev, hits, st);
   return launch4<false>(s, rays, idx, n_max, count_dev, hits, kDefaultRefill, nullptr, st);
 }
 
@@ -471,10 +703,14 @@ rr_status launch_trace_refill(const DeviceScene& s, const rr_ray* rays, const ui
 
 rr_status launch_trace_any(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
                            const uint32_t* count_dev, rr_hit* hits, hipStream_t st) {
+  if (n_max <= 0) return RR_OK;
+  if (s.quantised && n_max <= quad_capacity())
+    return launch_quad<true>(s, rays, idx, n_max, count_dev, hits, st);
   return launch4<false, true>(s, rays, idx, n_max, count_dev, hits, kDefaultRefill, nullptr, st);
 }
 
 void trace_warm() {
+  (void)quad_capacity();
   (void)resident_blocks<kTraceBlock, false, false, false>();
   (void)resident_blocks<kTraceBlock, false, true, false>();
   (void)resident_blocks<kTraceBlock, true, false, false>();

@@ -301,6 +301,43 @@ def test_trace_ragged_counts_and_refill(rr, soup65k):
     assert_hits_match(rr.hits_to_numpy(full), ref, rays, w.tris, "full")
 
 
+def test_four_lane_trace_equals_the_persistent_kernel(rr):
+    """rr_trace traces small launches with four lanes per ray (up to what one
+    resident wave of its blocks holds, about 98K rays) and larger ones with
+    one lane per ray; rr_trace_ex always takes the latter.  On bounce-2 rays
+    of the city both give the same hits bit for bit on both sides of the
+    switch, with a device count below the capacity, and through an index
+    (the fused call's indirect trace); a sample is checked against the
+    oracle."""
+    w = W.city_small(seed=11, width=480, height=270, depth=1)
+    rays = np.ascontiguousarray(w.rays)
+    n_all = rays.shape[0]
+    assert n_all > 110000
+    bvh = O.BVH(w.tris)
+    with rr.Scene(w.tris) as sc:
+        dr = to_dev(rays)
+        for n in (1, 3, 64, 65, 4097, 65536, 98303, 98304, 98305, 110001):
+            r = dr[:n]
+            a = rr.rr_trace(sc, r)
+            b = rr.rr_trace(sc, r, refill=8)
+            assert torch.equal(a.view(torch.int32), b.view(torch.int32)), n
+        n = 90000
+        cnt = torch.tensor([54321], dtype=torch.int32, device=DEV)
+        out = torch.full((n, 4), -3.0, dtype=torch.float32, device=DEV)
+        rr.rr_trace(sc, dr[:n], count=cnt, hits=out)
+        full = rr.rr_trace(sc, dr[:n], refill=8)
+        assert torch.equal(out[:54321].view(torch.int32), full[:54321].view(torch.int32))
+        assert bool((out[54321:] == -3.0).all())
+        sample = W.sample_indices(11, 7, 4096, n)
+        assert_hits_match(rr.hits_to_numpy(full)[sample], bvh.trace(rays[sample]), rays[sample], w.tris, "sample")
+        lo, hi = sc.bounds()
+        p = rr.key_params(O.KIND_OD, 32, lo, hi, 0.25)
+        for flags in (rr.RR_INDIRECT, rr.RR_INDIRECT | rr.RR_HITS_ORIGINAL_ORDER, rr.RR_HITS_ORIGINAL_ORDER):
+            h, _, _ = rr.rr_reorder_and_trace(sc, dr[:n], p, flags=flags)
+            if flags & rr.RR_HITS_ORIGINAL_ORDER:
+                assert torch.equal(h.view(torch.int32), full.view(torch.int32)), flags
+
+
 def test_trace_tiny_scenes_and_ties(rr):
     # one triangle (the root is a leaf); shared-edge tie goes to the lower id
     a = [1, 0, 0.5, 0, 1, 0.5, 1, 1, 0.5]
@@ -385,6 +422,10 @@ def test_trace_deep_stack_spills_to_scratch(rr, builder):
         assert prof["max_stack"] > 16 and prof["spill_pushes"] > 0, prof
         h = rr.hits_to_numpy(rr.rr_trace(sc, rd))
         assert_hits_match(h, ref, rays, T, f"stack builder {builder}")
+        # the persistent one-lane-per-ray kernel (rr_trace_ex; rr_trace takes the
+        # four-lane kernel at this size) spills too and gives the same hits
+        h1 = rr.hits_to_numpy(rr.rr_trace(sc, rd, refill=8))
+        assert h1.tobytes() == h.tobytes()
         # the profiling variant returns the same hits
         hp = torch.empty((rays.shape[0], 4), dtype=torch.float32, device=DEV)
         rr.rr_trace_profile(sc, rd, hits=hp)
