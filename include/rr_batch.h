@@ -94,11 +94,12 @@ rr_status rr_batch_destroy(rr_batch b);
 typedef struct rr_server_config {
   int32_t slots;             /* concurrent batches (streams), >= 1 */
   int64_t hbm_budget_bytes;  /* device memory the server may hold for batch workspaces */
-  int64_t max_batch_rays;    /* largest batch (and largest request) */
+  int64_t max_batch_rays;    /* largest batch (and largest request or part) */
   int32_t max_batch_requests;  /* segments (requests or parts) per batch */
-  int64_t split_rays;        /* 0, or: a request in ray order larger than this is served as
-                                consecutive parts of at most split_rays rays, each reordered and
-                                traced as a segment of its own (its hits do not change) */
+  int64_t split_rays;        /* 0, or (at most max_batch_rays): a request in ray order larger
+                                than this is served as consecutive parts of at most split_rays
+                                rays, each reordered and traced as a segment of its own (its
+                                hits do not change) */
 } rr_server_config;
 
 typedef struct rr_request_stats {
@@ -129,7 +130,8 @@ rr_status rr_server_start(rr_server sv);
 /* Queues a request (no device work in the call).  arrival_s < 0 means now.
  * flags: RR_HITS_ORIGINAL_ORDER (hits[i] belongs to rays[i]) or 0 (hits in
  * the request's key order); a batch holds requests of one hit order.
- * A request larger than max_batch_rays is rejected with RR_ERR_BUDGET.
+ * A request larger than max_batch_rays is rejected with RR_ERR_BUDGET,
+ * unless it is served as parts (each of at most split_rays rays).
  * The rays must be complete in device memory when rr_server_submit is
  * called: the server's streams read them without waiting for the stream
  * that produced them.  The ray and hit buffers must stay valid until the

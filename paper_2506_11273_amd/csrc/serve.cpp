@@ -220,7 +220,7 @@ rr_status rr_server_create(rr_scene s, const rr_server_config* cfg, rr_server* o
   *out = nullptr;
   if (!s || !cfg || cfg->slots < 1 || cfg->slots > 16 || cfg->max_batch_rays <= 0 ||
       cfg->max_batch_rays >= RR_MAX_RAYS || cfg->max_batch_requests < 1 || cfg->max_batch_requests > 4096 ||
-      cfg->hbm_budget_bytes <= 0 || cfg->split_rays < 0)
+      cfg->hbm_budget_bytes <= 0 || cfg->split_rays < 0 || cfg->split_rays > cfg->max_batch_rays)
     return RR_ERR_INVALID_ARGUMENT;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != s->d.device) return RR_ERR_INVALID_ARGUMENT;
@@ -291,8 +291,13 @@ rr_status rr_server_submit(rr_server sv, const rr_ray* rays, int64_t n, const rr
   }
   // a bad request is refused here so that it never fails its batch-mates
   if (n > 0 && (!device_ptr(rays, 16) || !device_ptr(hits, 16))) return RR_ERR_INVALID_ARGUMENT;
+  // parts: only a request in ray order is split (its hits do not depend on
+  // the split); an empty request is one empty part.  Every part must fit a
+  // batch.
+  const int64_t split = sv->cfg.split_rays;
+  const int64_t part = (flags & RR_HITS_ORIGINAL_ORDER) && split > 0 && n > split ? split : std::max<int64_t>(n, 1);
   std::lock_guard<std::mutex> lk(sv->mu);
-  if (n > sv->cfg.max_batch_rays) {
+  if (part > sv->cfg.max_batch_rays) {
     ++sv->rejected;
     return RR_ERR_BUDGET;
   }
@@ -305,10 +310,6 @@ rr_status rr_server_submit(rr_server sv, const rr_ray* rays, int64_t n, const rr
   r.hits = hits;
   r.key = *key;
   r.flags = flags;
-  // parts: only a request in ray order is split (its hits do not depend on
-  // the split); an empty request is one empty part
-  const int64_t split = sv->cfg.split_rays;
-  const int64_t part = (flags & RR_HITS_ORIGINAL_ORDER) && split > 0 && n > split ? split : std::max<int64_t>(n, 1);
   std::vector<Part> parts;
   for (int64_t off = 0; off == 0 || off < n; off += part) {
     const int64_t m = std::min(part, n - off);

@@ -377,6 +377,33 @@ def test_server_destroy_releases_waiting_threads(rr, city):
     assert sorted(out) == sorted(ids) and all(v != "ok" for v in out.values())
 
 
+def test_server_requests_larger_than_a_batch_as_parts(rr, city):
+    """A request in ray order larger than the largest batch is served as
+    parts of the split size (its hits equal the request traced alone); one
+    in key order, which cannot be split, is refused; a split size larger
+    than the largest batch is refused at create."""
+    w, scene = city
+    with pytest.raises(rr.RRError) as e:
+        rr.Server(scene, slots=2, hbm_budget_bytes=8 << 30, max_batch_rays=20000, split_rays=30000)
+    assert e.value.status == -1
+    segs = make_segments(rr, w, scene, [50000, 50000, 7000], seed=71)
+    with rr.Server(scene, slots=2, hbm_budget_bytes=8 << 30, max_batch_rays=20000, max_batch_requests=4,
+                   split_rays=5000) as sv:
+        sv.start()
+        a = sv.submit(segs[0]["rays"], segs[0]["hits"], segs[0]["key"])
+        with pytest.raises(rr.RRError) as e:
+            sv.submit(segs[1]["rays"], segs[1]["hits"], segs[1]["key"], flags=0)
+        assert e.value.status == -6
+        c = sv.submit(segs[2]["rays"], segs[2]["hits"], segs[2]["key"], flags=0)
+        sv.drain(60.0)
+        assert sv.wait(a)["status"] == 0 and sv.wait(c)["status"] == 0
+        assert sv.stats()["rejected"] == 1
+    hits, _ = expected(rr, scene, segs[0])
+    assert rr.hits_to_numpy(segs[0]["hits"]).tobytes() == hits.tobytes()
+    hits, perm = expected(rr, scene, segs[2])
+    assert rr.hits_to_numpy(segs[2]["hits"]).tobytes() == hits[perm].tobytes()
+
+
 def test_server_splits_large_requests(rr, city):
     """With a split size, requests in ray order larger than it are served as
     parts (several batches, possibly on several slots at once); requests in
