@@ -839,9 +839,11 @@ def batched(torch, rr, W, scene, w, dev, stream):
     return out
 
 
-# the server's shape in the served section: 4 slots, requests in ray order
-# above 512K rays served as parts of 512K
-SERVE_SHAPE = dict(slots=4, hbm_budget_bytes=32 << 30, max_batch_rays=1 << 23, max_batch_requests=16,
+# the server's shape in the served section: 3 slots, batches of at most 2M
+# rays, requests in ray order above 512K rays served as parts of 512K (every
+# request of a batch completes with the batch, and concurrent batches share
+# the device, so smaller batches shorten the latency tail)
+SERVE_SHAPE = dict(slots=3, hbm_budget_bytes=32 << 30, max_batch_rays=1 << 21, max_batch_requests=16,
                    split_rays=1 << 19)
 # the earlier shape (2 slots, no parts), run at 0.8 load for comparison
 SERVE_SHAPE_2SLOTS = dict(slots=2, hbm_budget_bytes=32 << 30, max_batch_rays=1 << 23, max_batch_requests=16,

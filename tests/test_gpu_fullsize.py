@@ -125,7 +125,8 @@ def test_batch_64_wavefronts(rr, city):
 
 def test_served_4m_city(rr):
     """The serving configuration of the bench (~4M-triangle city, requests
-    of 16K to 4M rays with mixed key methods, two slots, 32 GB budget): every
+    of 16K to 4M rays with mixed key methods; three slots, batches of at most
+    2M rays, requests above 512K rays served as parts; 32 GB budget): every
     served hit equals the unsorted trace of its request and the oracle's
     trace of the request."""
     c = W.city(5, 200, 200, 3_520_000)
@@ -144,8 +145,8 @@ def test_served_4m_city(rr):
             kind, bits = kinds[j % len(kinds)]
             reqs.append((rn, to_dev(rn), torch.empty((n, 4), dtype=torch.float32, device=DEV),
                          rr.key_params(kind, bits, lo, hi, 0.25)))
-        with rr.Server(scene, slots=2, hbm_budget_bytes=32 << 30, max_batch_rays=1 << 23,
-                       max_batch_requests=16) as sv:
+        with rr.Server(scene, slots=3, hbm_budget_bytes=32 << 30, max_batch_rays=1 << 21,
+                       max_batch_requests=16, split_rays=1 << 19) as sv:
             sv.start()
             ids = [sv.submit(rd, h, p, arrival_s=0.0005 * j) for j, (_, rd, h, p) in enumerate(reqs)]
             sv.drain(300.0)
