@@ -374,7 +374,8 @@ def config1(torch, rr, W, dev, stream, reps=50):
     triangles, median-split BVH, 32-bit origin-direction keys.  Per fused
     call: device time (HIP events, median), wall time per call with the
     calls issued back to back, and the host time to issue one call (no
-    synchronisation inside the issuing loop); the unsorted trace alike."""
+    synchronisation inside the issuing loop); the unsorted trace alike, and
+    that trace through the persistent one-lane kernel for comparison."""
     w = W.soup(seed=1)
     n = w.rays.shape[0]
     out = {"rays": int(n), "triangles": int(w.tris.shape[0]), "bvh": "median split collapsed to 4-wide",
@@ -407,6 +408,16 @@ def config1(torch, rr, W, dev, stream, reps=50):
                          "wall_ms_per_call": round((t2 - t0) * 1e3 / reps, 4),
                          "host_issue_us_per_call": round((t1 - t0) * 1e6 / reps, 1)}
         out["reorder_vs_unsorted"] = round(out["unsorted_trace"]["device_ms"] / out["fused"]["device_ms"], 3)
+        # the same trace through the persistent one-lane kernel (rr_trace_ex),
+        # which rr_trace leaves for launches of this size to the four-lane one
+        one = torch.empty_like(hits)
+        rr.rr_trace(sc, rays, hits=one, refill=8)
+        ms1 = median_ms(torch, stream, lambda: rr.rr_trace(sc, rays, hits=one, refill=8), reps)
+        rr.rr_trace(sc, rays, hits=hits)
+        torch.cuda.synchronize()
+        out["unsorted_trace_one_lane_kernel_ms"] = round(ms1, 4)
+        out["four_lane_vs_one_lane"] = round(ms1 / out["unsorted_trace"]["device_ms"], 3)
+        out["four_lane_hits_equal_one_lane"] = bool(torch.equal(one.view(torch.int32), hits.view(torch.int32)))
     return out
 
 
