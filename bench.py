@@ -621,9 +621,10 @@ def sorts_only(torch, rr, W, dev, args):
     keys (2,073,600), random keys (8,294,400), random keys (67,108,864, more
     than the 256 MB MALL holds); each input sorted by the most-significant-
     digit sort (rr_sort_msd: setup, histogram, two scatter passes with a
-    histogram between them, bucket kernel) and then by the LSD sort
-    (rr_sort_ex with rr_sort's tile size: setup, histogram, 8 scatter
-    passes)."""
+    histogram between them, then both bucket kernels, of which one returns
+    at once: the wave kernel when no bucket holds more than 512 keys, else
+    the batch kernel) and then by the LSD sort (rr_sort_ex with rr_sort's
+    tile size: setup, histogram, 8 scatter passes)."""
     w = W.bounce2_1080p()
     with rr.Scene(w.tris) as sc:
         lo, hi = sc.bounds()
@@ -724,9 +725,10 @@ def bounce3(torch, rr, W, scene, dev, stream, steps):
 def sort_sizes(torch, rr, dev, stream, reps=7):
     """rr_sort of seeded uniform random keys with indices 0..n-1 at the two
     wavefront sizes and at 64M pairs (beyond the 256 MB last-level cache),
-    32- and 64-bit keys, against the HBM roofline of the 8-bit schedule; each
-    result is checked (keys non-decreasing as unsigned words, equal keys in
-    ascending index order, indices a permutation)."""
+    32- and 64-bit keys, against the HBM roofline of the 8-bit schedule; for
+    64-bit keys also rr_sort_msd of the same keys (entries ending in _msd).
+    Each result is checked (keys non-decreasing as unsigned words, equal keys
+    in ascending index order, indices a permutation)."""
     out = {}
     for n in (2073600, 8294400, 67108864):
         for bits in (32, 64):
@@ -739,28 +741,31 @@ def sort_sizes(torch, rr, dev, stream, reps=7):
             k = torch.empty_like(k0)
             i = torch.empty_like(i0)
             ws = rr.workspace(rr.sort_workspace_size(n, bits), dev)
-            times = []
-            for _ in range(reps):
-                k.copy_(k0)
-                i.copy_(i0)
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                rr.rr_sort(k, i, key_bits=bits, ws=ws)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                times.append(e0.elapsed_time(e1))
-            ms = float(np.median(times[1:]))
-            flip = k ^ torch.tensor(lo, dtype=dt, device=dev)  # unsigned order as signed order
-            ok = bool((flip[1:] >= flip[:-1]).all())
-            ties = flip[1:] == flip[:-1]
-            ok = ok and bool((i[1:][ties] > i[:-1][ties]).all())
-            ok = ok and bool(torch.equal(torch.sort(i).values, i0))
-            ok = ok and bool(torch.equal(k0[i.long()], k))
-            b = sort_algorithmic_bytes(n, bits)
-            out[f"u{bits}_n{n}"] = {"ms": round(ms, 4), "gbs": round(b / (ms * 1e-3) / 1e9, 1),
-                                    "roofline_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3), "ok": ok}
-            del k0, i0, k, i, ws, flip, ties
+            for msd in ((False, True) if bits == 64 else (False,)):
+                times = []
+                for _ in range(reps):
+                    k.copy_(k0)
+                    i.copy_(i0)
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    rr.rr_sort(k, i, key_bits=bits, ws=ws, msd=msd)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    times.append(e0.elapsed_time(e1))
+                ms = float(np.median(times[1:]))
+                flip = k ^ torch.tensor(lo, dtype=dt, device=dev)  # unsigned order as signed order
+                ok = bool((flip[1:] >= flip[:-1]).all())
+                ties = flip[1:] == flip[:-1]
+                ok = ok and bool((i[1:][ties] > i[:-1][ties]).all())
+                ok = ok and bool(torch.equal(torch.sort(i).values, i0))
+                ok = ok and bool(torch.equal(k0[i.long()], k))
+                b = sort_algorithmic_bytes(n, bits)
+                out[f"u{bits}_n{n}" + ("_msd" if msd else "")] = {
+                    "ms": round(ms, 4), "gbs": round(b / (ms * 1e-3) / 1e9, 1),
+                    "roofline_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3), "ok": ok}
+                del flip, ties
+            del k0, i0, k, i, ws
             torch.cuda.empty_cache()
     return out
 

@@ -221,11 +221,8 @@ rr_status rr_coherence_m64(const rr_ray* rays, const rr_hit* hits, int64_t n, co
  * Section 3.2: stable ascending radix sort of (key, index) pairs, in place.
  * The result is unique: the lexicographic order of (key, index) when the
  * input indices ascend (in general: by key, equal keys in input position
- * order).  For 64-bit keys with n_max from 12,582,912 up to 2^27 rr_sort runs
- * a most-significant-digit sort (two stable scatter passes on the two highest
- * 8-bit digits in which the keys differ, then every bucket of equal top digits
- * sorted on its other digits in LDS); otherwise an LSD sort with 8-bit digits
- * (the faster one outside that range).  n_max is the capacity; when count_dev
+ * order).  rr_sort runs an LSD sort with 8-bit digits (one histogram pass,
+ * then one stable scatter pass per digit).  n_max is the capacity; when count_dev
  * (device uint32) is given, only its first *count_dev pairs are sorted
  * (count_dev must not exceed n_max).  workspace (device, >= the size
  * reported by rr_sort_workspace_size, 256-byte aligned) is scratch that the
@@ -236,15 +233,20 @@ rr_status rr_coherence_m64(const rr_ray* rays, const rr_hit* hits, int64_t n, co
 rr_status rr_sort_workspace_size(int64_t n_max, uint32_t key_bits, size_t* bytes);
 rr_status rr_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                   void* workspace, size_t ws_bytes, void* stream);
-/* The most-significant-digit sort at any size it supports: 64-bit keys with
- * n_max below 2^27 (otherwise RR_ERR_UNSUPPORTED).  Arguments, workspace and
- * result as for rr_sort. */
+/* The most-significant-digit sort: two stable scatter passes on the two
+ * highest 8-bit digits in which the keys differ, then every bucket of equal
+ * top digits sorted on its other digits in LDS.  64-bit keys with n_max below
+ * 2^27 (otherwise RR_ERR_UNSUPPORTED).  Arguments, workspace and result as
+ * for rr_sort.  Faster than rr_sort when every bucket holds at most 512 keys
+ * (evenly spread keys from about 2M to 17M pairs, where each bucket is sorted
+ * by one wave); slower for clustered keys such as the paper's ray keys, whose
+ * large buckets are sorted by whole blocks. */
 rr_status rr_sort_msd(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                       void* workspace, size_t ws_bytes, void* stream);
 /* The LSD sort with an explicit radix digit width (4 or 8 bits) and keys
  * per thread (tile size); every choice gives the identical result, that of
- * rr_sort.  rr_sort's LSD sort and scatter passes use 8-bit digits and 8 keys
- * per thread, 16 from 2^24 keys (n_max) on. */
+ * rr_sort.  rr_sort uses 8-bit digits and 8 keys per thread, 16 from 2^24
+ * keys (n_max) on. */
 rr_status rr_sort_ex(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                      uint32_t digit_bits, uint32_t keys_per_thread, void* workspace, size_t ws_bytes,
                      void* stream);
@@ -345,7 +347,7 @@ rr_status rr_trace_profile(rr_scene s, const rr_ray* rays, int64_t n, rr_hit* hi
  * learns from closest hits. */
 #define RR_ANY_HIT 32u
 /* The device-wide sort is the most-significant-digit sort (rr_sort_msd)
- * whatever the size: 64-bit keys and n below 2^27 (otherwise
+ * instead of rr_sort's LSD sort: 64-bit keys and n below 2^27 (otherwise
  * RR_ERR_UNSUPPORTED); not with RR_LOCAL_SORT_* (RR_ERR_INVALID_ARGUMENT);
  * no effect with RR_KEY_NONE. */
 #define RR_SORT_MSD 64u

@@ -96,10 +96,9 @@ bool sort_config_supported(uint32_t key_bits, uint32_t digit_bits, uint32_t kpt)
 // The LSD sort with an explicit digit width and tile size.
 rr_status launch_sort(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                       uint32_t digit_bits, uint32_t kpt, void* ws, size_t ws_bytes, hipStream_t st);
-// rr_sort's choice: the most-significant-digit sort for 64-bit keys from
-// 12,582,912 up to 2^27 keys (n_max), else the LSD sort with 8-bit digits;
-// force_msd takes the most-significant-digit sort at any size it supports
-// (64-bit keys below 2^27, else RR_ERR_UNSUPPORTED).
+// rr_sort: the LSD sort with 8-bit digits; force_msd takes the
+// most-significant-digit sort instead (64-bit keys below 2^27, else
+// RR_ERR_UNSUPPORTED).
 rr_status launch_sort_auto(void* keys, uint32_t* idx, int64_t n_max, const uint32_t* count_dev, uint32_t key_bits,
                            void* ws, size_t ws_bytes, hipStream_t st, bool force_msd = false);
 // The same sort with the ray gather fused into its last pass:

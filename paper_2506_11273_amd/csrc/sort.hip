@@ -58,6 +58,11 @@ constexpr uint32_t kGroupWindow = kGroup;     // group words read per look-back 
 constexpr uint32_t kFallbackSpins = 128;       // polls of an unpublished entry before computing it
 constexpr uint32_t kFallbackSpinsCounted = 1u << 16;  // tiles from the counter: waiting is always safe
 constexpr uint32_t kHistUnit = 4096;  // keys per histogram work unit (8 per thread)
+// Buckets of the most-significant-digit sort of at most kWaveCap keys can
+// each be sorted by one wave (k_msd_wave): when every bucket is that small,
+// k_msd_wave sorts them all and k_msd_local has nothing to do, else
+// k_msd_local sorts them all.
+constexpr uint32_t kWaveCap = 512;
 constexpr uint32_t kHistCopies = 8;   // histogram copies of a single-segment sort (one per XCD)
 constexpr uint32_t kHistLaneCopies = 8;  // LDS histogram copies per block, lane l counts into copy l % 8
 constexpr uint32_t kHistCopyPad = 8;     // words between LDS copies beyond their size: copy c starts 8c banks on
@@ -141,7 +146,7 @@ __global__ void k_msd_setup(const uint32_t* count_dev, uint32_t n_max, uint32_t 
     segs[0] = SortSeg{0u, n, 0u, tiles};
     *hdr = SortHdr{1u, tiles, n, 0u};
     *hdr2 = SortHdr{0u, 0u, 0u, 0u};
-    *plan = MsdPlan{1u, 0u, 0u, 0u};
+    *plan = MsdPlan{1u, 0u, 0u, 0u};  // no bucket larger than kWaveCap yet
   }
 }
 
@@ -582,7 +587,10 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
       const uint32_t ex = block_scan(h, sm.scan, &total);
       if (tid < R) sm.base[tid] = sg.off + ex;
       if constexpr (MODE == 2) {
-        if (lt == 0 && tid < R) msd.bstart[(size_t)s * R + tid] = sg.off + ex;
+        if (lt == 0 && tid < R) {
+          msd.bstart[(size_t)s * R + tid] = sg.off + ex;
+          if (h > kWaveCap) atomicOr(&msd.plan->big, 1u);
+        }
       }
       if constexpr (MODE == 1) {
         // the segments of the second pass: one per value of digit dh
@@ -972,7 +980,7 @@ __global__ __launch_bounds__(kLocThreads) void k_msd_local(K* __restrict__ keys,
   constexpr uint32_t P = sizeof(K);
   const uint32_t n = hdr->total_keys;
   const uint32_t wb = blockIdx.x * kLocWindow;
-  if (wb >= n) return;
+  if (wb >= n || !plan->big) return;  // k_msd_wave has sorted every bucket
   const uint32_t we = min(n, wb + kLocWindow);
   const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1);
   for (uint32_t i = tid; i < 2 * kLocWaves * 256; i += kLocThreads) (&sm.wave_hist[0][0][0])[i] = 0;
@@ -1084,6 +1092,136 @@ __global__ __launch_bounds__(kLocThreads) void k_msd_local(K* __restrict__ keys,
     }
     p0 += nb;
     __syncthreads();  // sm.keys and sm.red are reused by the next batch
+  }
+}
+
+// The last kernel of the most-significant-digit sort when every (dh, dl)
+// bucket holds at most kWaveCap keys (random keys up to ~16M pairs): wave w
+// sorts bucket w alone (a bucket's passes are a chain of dependent LDS
+// operations, so every bucket gets a wave of its own), the keys in
+// registers (kWaveKpt per lane, position lane + 64 j), by stable counting
+// passes over the digits other than dh and dl in which the
+// bucket's keys differ, least significant first.  A pass ranks the keys
+// row by row with wave64 ballots (the lowest lane of each group of equal
+// digits adds the group's size to the wave's counter with one LDS atomic),
+// scans the 256 counters across the wave and moves the keys through the
+// wave's own LDS; one wave's LDS operations take effect in order, so no
+// barrier is needed.  A bucket sits at [bstart, bstart + bcount) after the
+// dl pass and the keys there are in input order, so the result is the
+// stable sort.  The gather of the fused call moves each ray to its slot.
+constexpr int kWaveThreads = 256;
+constexpr int kWaveWaves = kWaveThreads / kWave;
+constexpr int kWaveKpt = kWaveCap / kWave;
+constexpr uint32_t kBuckets = 1u << 16;
+constexpr uint32_t kWaveGrid = kBuckets / kWaveWaves;  // one wave per bucket
+
+template <typename K>
+struct WaveSmem {
+  K keys[kWaveWaves][kWaveCap];
+  uint32_t idx[kWaveWaves][kWaveCap];
+  uint32_t cnt[kWaveWaves][256];
+};
+
+template <typename K>
+__global__ __launch_bounds__(kWaveThreads) void k_msd_wave(K* __restrict__ keys, uint32_t* __restrict__ idx,
+                                                           const MsdPlan* plan, const uint32_t* __restrict__ bstart,
+                                                           const uint32_t* __restrict__ bcount,
+                                                           const float4* __restrict__ gather_in,
+                                                           float4* __restrict__ gather_out, uint32_t gather_n) {
+  if (plan->big) return;  // k_msd_local sorts every bucket
+  __shared__ WaveSmem<K> sm;
+  constexpr uint32_t P = sizeof(K);
+  const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  K* const lk = sm.keys[wv];
+  uint32_t* const li = sm.idx[wv];
+  uint32_t* const lc = sm.cnt[wv];
+  const uint32_t b = blockIdx.x * kWaveWaves + wv;  // this wave's bucket
+  const uint32_t dh = plan->dh, dl = plan->dl;
+  const uint32_t m = b < kBuckets ? bcount[b] : 0u;
+  if (m == 0) return;
+  const uint32_t p0 = bstart[b];
+  const uint32_t rows = (m + kWave - 1) / kWave;  // rows of keys in use
+  K k[kWaveKpt];
+  uint32_t v[kWaveKpt];
+#pragma unroll
+  for (int j = 0; j < kWaveKpt; ++j) {
+    const uint32_t p = lane + kWave * j;
+    k[j] = p < m ? keys[p0 + p] : (K)0;
+    v[j] = p < m ? idx[p0 + p] : 0u;
+  }
+  bool moved = false;
+  if (m > 1) {
+    // digits in which the bucket's keys differ
+    const K kf = (K)__shfl((unsigned long long)k[0], 0, kWave);
+    uint64_t diff = 0;
+#pragma unroll
+    for (int j = 0; j < kWaveKpt; ++j)
+      if (lane + kWave * j < m) diff |= (uint64_t)(k[j] ^ kf);
+    uint32_t dm = 0;
+#pragma unroll
+    for (uint32_t d = 0; d < P; ++d)
+      if (__ballot(((diff >> (8 * d)) & 255u) != 0)) dm |= 1u << d;
+#pragma unroll 1
+    for (uint32_t d = 0; d < P; ++d) {
+      if (d == dh || d == dl || ((dm >> d) & 1u) == 0) continue;
+      moved = true;
+      for (uint32_t i = lane; i < 256; i += kWave) lc[i] = 0;
+      uint32_t dg[kWaveKpt], rank[kWaveKpt], old[kWaveKpt];
+#pragma unroll
+      for (int j = 0; j < kWaveKpt; ++j) {
+        dg[j] = 0;
+        rank[j] = 0;
+        old[j] = 0;
+        if ((uint32_t)j < rows) {  // wave-uniform
+          const uint32_t p = lane + kWave * j;
+          const bool ok = p < m;
+          dg[j] = (uint32_t)(k[j] >> (8 * d)) & 255u;
+          const uint64_t peers = match_digit<8>(dg[j], __ballot(ok));
+          const uint32_t leader = ok ? (uint32_t)__builtin_ctzll(peers) : lane;
+          rank[j] = lanes_below(peers) | (leader << 16);
+          if (ok && lane == leader) old[j] = atomicAdd(&lc[dg[j]], (uint32_t)__popcll(peers));
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kWaveKpt; ++j)
+        if ((uint32_t)j < rows)
+          rank[j] = (rank[j] & 0xFFFFu) + (uint32_t)__shfl((int)old[j], (int)(rank[j] >> 16), kWave);
+      // exclusive offsets of the 256 digits: lane l owns digits 4l .. 4l + 3
+      const uint32_t c0 = lc[4 * lane], c1 = lc[4 * lane + 1], c2 = lc[4 * lane + 2], c3 = lc[4 * lane + 3];
+      uint32_t tot;
+      const uint32_t ex = wave_scan_excl(c0 + c1 + c2 + c3, &tot);
+      lc[4 * lane] = ex;
+      lc[4 * lane + 1] = ex + c0;
+      lc[4 * lane + 2] = ex + c0 + c1;
+      lc[4 * lane + 3] = ex + c0 + c1 + c2;
+#pragma unroll
+      for (int j = 0; j < kWaveKpt; ++j) {
+        if (lane + kWave * j < m) {
+          const uint32_t at = lc[dg[j]] + rank[j];
+          lk[at] = k[j];
+          li[at] = v[j];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kWaveKpt; ++j) {
+        const uint32_t p = lane + kWave * j;
+        if (p < m) {
+          k[j] = lk[p];
+          v[j] = li[p];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kWaveKpt; ++j) {
+    const uint32_t p = lane + kWave * j;
+    if (p < m) {
+      if (moved) {
+        if (!gather_out) keys[p0 + p] = k[j];
+        idx[p0 + p] = v[j];
+      }
+      if (gather_out) loc_gather_one(gather_in, gather_out, gather_n, p0 + p, v[j]);
+    }
   }
 }
 
@@ -1268,6 +1406,9 @@ rr_status msd_sort_impl(K* keys, uint32_t* idx, const SegLayout& L, char* ws, co
                      status2 + L.status2_stride, gstatus2 + L.gstatus2_stride, (uint32_t*)nullptr,
                      (const float4*)nullptr, (float4*)nullptr, 0u, MsdArgs{2u, plan, nullptr, nullptr, bstart});
   // every (dh, dl) bucket on its remaining digits (and the ray gather)
+  hipLaunchKernelGGL((k_msd_wave<K>), dim3(kWaveGrid), dim3(kWaveThreads), 0, st, keys, idx, (const MsdPlan*)plan,
+                     bstart, hist2, reinterpret_cast<const float4*>(gather_in), reinterpret_cast<float4*>(gather_out),
+                     gather_n);
   hipLaunchKernelGGL((k_msd_local<K>), dim3(msd_local_blocks<K>(n_max)), dim3(kLocThreads), 0, st, keys, idx, kalt,
                      ialt, hdr, plan, bstart, hist2, reinterpret_cast<const float4*>(gather_in),
                      reinterpret_cast<float4*>(gather_out), gather_n);
@@ -1314,17 +1455,17 @@ SegLayout msd_layout(int64_t n_max, uint32_t key_bits, uint32_t kpt) {
   return L;
 }
 
-// From 2^27 pairs on the buckets average over 2K keys.  Below about 12M
-// pairs the LSD sort is as fast or faster: its eight scatter passes are
-// short, while the bucket kernel's chains of in-LDS passes run on fewer
-// blocks than there are CUs' worth of work to hide them.
+// Which of the two sorts is faster depends on the keys.  Evenly spread keys
+// from ~2M to ~17M pairs fill every (dh, dl) bucket with at most kWaveCap
+// keys, so k_msd_wave sorts the buckets and the MSD sort beats the LSD sort.
+// Clustered keys such as ray keys leave large buckets to k_msd_local, whose
+// chains of in-LDS passes run on one block per CU, and the LSD sort is then
+// as fast or faster.  Hence rr_sort keeps the LSD sort.  From 2^27 pairs on
+// even evenly spread keys give buckets of over 2K keys.
 bool msd_supported(int64_t n_max, uint32_t key_bits) {
   return key_bits == 64 && n_max > 0 && n_max < (int64_t(1) << 27);
 }
 
-bool msd_preferred(int64_t n_max, uint32_t key_bits) {
-  return msd_supported(n_max, key_bits) && n_max >= kMsdMinKeys;
-}
 
 SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_t db, uint32_t kpt) {
   SegLayout L{};
@@ -1445,7 +1586,7 @@ rr_status launch_sort_auto(void* keys, uint32_t* idx, int64_t n_max, const uint3
   if (key_bits != 32 && key_bits != 64) return RR_ERR_UNSUPPORTED;
   if (force_msd && !msd_supported(n_max, key_bits)) return RR_ERR_UNSUPPORTED;
   const uint32_t kpt = sort_default_kpt(n_max);
-  if (force_msd || msd_preferred(n_max, key_bits))
+  if (force_msd)
     return launch_msd(keys, idx, n_max, count_dev, key_bits, kpt, ws, ws_bytes, nullptr, nullptr, 0u, st, nullptr);
   return launch_sort(keys, idx, n_max, count_dev, key_bits, 8, kpt, ws, ws_bytes, st);
 }
@@ -1468,7 +1609,7 @@ rr_status launch_keys_sort_gather(const rr_ray* rays, int64_t n, const KeyPlan& 
     return RR_ERR_UNSUPPORTED;
   if (force_msd && !msd_supported(n, key_bits)) return RR_ERR_UNSUPPORTED;
   const KeySource src{rays, plan};
-  if (force_msd || msd_preferred(n, key_bits))
+  if (force_msd)
     return launch_msd(keys, idx, n, nullptr, key_bits, kpt, ws, ws_bytes, rays, rays_out, (uint32_t)n, st, &src);
   const SegLayout L = seg_layout(n, 1, key_bits, 8, kpt);
   if (ws_bytes < L.total) return RR_ERR_WORKSPACE_TOO_SMALL;
@@ -1490,7 +1631,7 @@ rr_status launch_sort_gather(void* keys, uint32_t* idx, int64_t n_max, const uin
                              rr_ray* rays_out, hipStream_t st, bool force_msd) {
   if (!sort_config_supported(key_bits, db, kpt)) return RR_ERR_UNSUPPORTED;
   if (force_msd && (db != 8 || !msd_supported(n_max, key_bits))) return RR_ERR_UNSUPPORTED;
-  if (db == 8 && (force_msd || msd_preferred(n_max, key_bits)))
+  if (db == 8 && (force_msd))
     return launch_msd(keys, idx, n_max, count_dev, key_bits, kpt, ws, ws_bytes, rays_in, rays_out, (uint32_t)n_max, st,
                       nullptr);
   const SegLayout L = seg_layout(n_max, 1, key_bits, db, kpt);

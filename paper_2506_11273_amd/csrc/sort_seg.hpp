@@ -20,7 +20,8 @@ struct SortHdr {
 // highest 8-bit digit in which the keys differ, dl the next one below it
 // (any other digit when no lower one differs).
 struct MsdPlan {
-  uint32_t dh, dl, n, pad;
+  uint32_t dh, dl, n;
+  uint32_t big;  // nonzero when some (dh, dl) bucket holds more than kWaveCap keys
 };
 
 // hist holds hist_copies copies of every segment's digit histograms
@@ -44,11 +45,9 @@ SegLayout seg_layout(int64_t n_max, uint32_t max_seg, uint32_t key_bits, uint32_
 // kpt keys per thread in its two scatter passes).
 SegLayout msd_layout(int64_t n_max, uint32_t key_bits, uint32_t kpt);
 // The most-significant-digit sort exists for 64-bit keys below 2^27
-// (msd_supported); rr_sort and the fused call take it by themselves from
-// kMsdMinKeys keys on (msd_preferred), else the LSD sort.
-constexpr int64_t kMsdMinKeys = 3 << 22;  // 12,582,912
+// (msd_supported); rr_sort and the fused call run it only when asked to
+// (force_msd), else the LSD sort.
 bool msd_supported(int64_t n_max, uint32_t key_bits);
-bool msd_preferred(int64_t n_max, uint32_t key_bits);
 
 // Sorts every segment described by the device header and segment table
 // hdr / segs.  With hdr == nullptr one segment of min(*count_dev, n_max)

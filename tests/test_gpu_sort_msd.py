@@ -1,15 +1,15 @@
 """GPU parity of the most-significant-digit sort (rr_sort_msd, and the fused
-call with RR_SORT_MSD; rr_sort takes it by itself for 64-bit keys from
-12,582,912 keys on): two stable scatter passes on the two highest digits in
-which the keys differ, then every bucket of equal top digits sorted on its
-other digits in LDS, or, when it holds more keys than fit, by one block in
+call with RR_SORT_MSD): two stable scatter passes on the two highest digits
+in which the keys differ, then the buckets of equal top digits sorted on
+their other digits: each by one wave when no bucket holds more than 512
+keys, else in batches in LDS, a bucket larger than a batch by one block in
 chunks through global memory.  Its result must be the stable order of the
-oracle (Section 3.2), and the LSD sort's (rr_sort_ex) bit for bit, whatever
-the key distribution: buckets that straddle the kernel's windows, buckets
-too large for LDS with an odd or even number of differing digits below the
-top two, keys differing in one digit only, input indices that do not
-ascend, a device count below the capacity; and rr_sort on both sides of the
-size from which it takes this sort."""
+oracle (Section 3.2), and the LSD sort's (rr_sort and rr_sort_ex) bit for
+bit, whatever the key distribution: buckets of 1 to 512 keys and one of 513,
+buckets that straddle the batch kernel's windows, buckets too large for LDS
+with an odd or even number of differing digits below the top two, keys
+differing in one digit only, input indices that do not ascend, a device
+count below the capacity, evenly spread keys at wavefront sizes."""
 import numpy as np
 import pytest
 
@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 DEV = "cuda"
-THRESHOLD = 12_582_912  # 64-bit keys from this size on take the MSD sort in rr_sort
+WAVE_CAP = 512  # largest bucket that one wave sorts
 
 
 @pytest.fixture(scope="module")
@@ -61,6 +61,73 @@ def run_all(rr, k, bits, idx_in=None, count=None, ways=None):
         assert np.array_equal(gk[:m], k[:m][perm]), ("keys", way)
         assert np.array_equal(gi[:m], idx_in[:m][perm]), ("idx", way)
         assert np.array_equal(gk[m:], k[m:]) and np.array_equal(gi[m:], idx_in[m:]), ("tail", way)
+
+
+def bucket_max(k):
+    """The largest bucket of the MSD sort for 64-bit keys k: keys of equal
+    digits dh and dl, dh the highest 8-bit digit in which the keys differ and
+    dl the next lower one that differs (dh alone when none does)."""
+    k = k.astype(np.uint64)
+    x = int(np.bitwise_or.reduce(k ^ k[0]))
+    digs = [d for d in range(8) if (x >> (8 * d)) & 255]
+    if not digs:
+        return int(k.size)
+    dh = max(digs)
+    b = (k >> np.uint64(8 * dh)) & np.uint64(255)
+    low = [d for d in digs if d < dh]
+    if low:
+        b = b * np.uint64(256) + ((k >> np.uint64(8 * max(low))) & np.uint64(255))
+    return int(np.bincount(b.astype(np.int64)).max())
+
+
+def wave_bucket_keys(seed, extra=()):
+    """Buckets (distinct top 16 bits) of 1 to 512 keys, the sizes around
+    every multiple of 64 (a wave's rows of keys) among them, plus the sizes in
+    extra.  In each bucket a random subset of the six lower digits varies
+    (none: all keys equal; all six: six in-wave passes).  Positions
+    shuffled."""
+    rng = np.random.default_rng(seed)
+    edges = [1, 2, 511, 512] + [64 * r + e for r in range(1, 8) for e in (-1, 0, 1)]
+    sizes = np.concatenate([rng.integers(1, 513, 300), edges, list(extra)]).astype(np.int64)
+    rng.shuffle(sizes)
+    prefixes = rng.choice(1 << 16, sizes.shape[0], replace=False).astype(np.uint64)
+    masks = np.zeros(sizes.shape[0], np.uint64)
+    for i in range(sizes.shape[0]):
+        for d in range(6):
+            if rng.random() < 0.6:
+                masks[i] |= np.uint64(255 << (8 * d))
+    masks[:3] = 0
+    masks[3:6] = np.uint64((1 << 48) - 1)
+    n = int(sizes.sum())
+    k = np.repeat(prefixes << np.uint64(48), sizes) | (rng.integers(0, 1 << 48, n, dtype=np.uint64)
+                                                       & np.repeat(masks, sizes))
+    return k[rng.permutation(n)], rng
+
+
+def test_every_bucket_sorted_by_one_wave(rr):
+    """Buckets of at most 512 keys: every bucket is sorted by one wave."""
+    k, rng = wave_bucket_keys(512)
+    assert bucket_max(k) == WAVE_CAP
+    run_all(rr, k, 64, idx_in=rng.permutation(k.shape[0]).astype(np.uint32))
+
+
+def test_one_bucket_of_513_keys(rr):
+    """The same kind of buckets and one of 513 keys: the batch kernel sorts
+    them all."""
+    k, rng = wave_bucket_keys(513, extra=(WAVE_CAP + 1,))
+    assert bucket_max(k) == WAVE_CAP + 1
+    run_all(rr, k, 64, idx_in=rng.permutation(k.shape[0]).astype(np.uint32))
+
+
+@pytest.mark.parametrize("n", [2_073_600, 8_294_400])
+def test_evenly_spread_keys_at_wavefront_sizes(rr, n):
+    """Uniform 64-bit keys of 1080p and 2160p wavefronts (buckets of ~32 and
+    ~127 keys, every one sorted by a wave) with a device count one below the
+    capacity."""
+    rng = np.random.default_rng(n)
+    k = rng.integers(0, (1 << 64) - 1, n, dtype=np.uint64, endpoint=True)
+    assert bucket_max(k[: n - 1]) <= WAVE_CAP
+    run_all(rr, k, 64, count=n - 1)
 
 
 def big_bucket_keys(n, bits, low_bits, frac, seed):
@@ -110,15 +177,6 @@ def test_small_and_window_sizes(rr, n):
     run_all(rr, k, 64)
 
 
-@pytest.mark.parametrize("n", [THRESHOLD - 1, THRESHOLD])
-def test_rr_sort_on_both_sides_of_the_threshold(rr, n):
-    """rr_sort just below (LSD sort) and at (MSD sort) the size from which
-    64-bit keys take the MSD sort; both give the oracle's order."""
-    rng = np.random.default_rng(n)
-    k = rng.integers(0, (1 << 64) - 1, n, dtype=np.uint64, endpoint=True) >> np.uint64(3)
-    run_all(rr, k, 64, ways=("auto",))
-
-
 @pytest.mark.parametrize("digit", [0, 1, 3])
 def test_one_or_two_differing_digits(rr, digit):
     """Keys that differ in one digit only, or in that digit and the top one:
@@ -166,6 +224,24 @@ def test_fused_call_with_a_bucket_larger_than_a_batch(rr):
                     assert_hits_match(h, back, rays, w.tris, f"{kind}/{flags}")
                 else:
                     assert_hits_match(h, ref["hits"], ref["rays"], w.tris, f"{kind}/{flags}")
+
+
+def test_fused_call_with_buckets_of_a_wave(rr):
+    """Distinct rays in a soup scene: the 64-bit keys fill buckets of a few
+    keys each, so the wave kernel sorts them and also gathers the rays; the
+    permutation equals the oracle's and the hits match under the closest-hit
+    rule."""
+    w = W.soup(seed=11, n_rays=120000, n_tris=2048)
+    bvh = O.BVH(w.tris)
+    with rr.Scene(w.tris) as sc:
+        lo, hi = sc.bounds()
+        for kind in (O.KIND_OD, O.KIND_OT):
+            ref = O.reorder_and_trace(bvh, w.rays, kind, 64, lo, hi, 0.25)
+            assert bucket_max(O.keys(w.rays, kind, 64, lo, hi, 0.25)) <= WAVE_CAP
+            p = rr.key_params(kind, 64, lo, hi, 0.25)
+            hits, perm, _ = rr.rr_reorder_and_trace(sc, to_dev(w.rays), p, flags=rr.RR_SORT_MSD)
+            assert np.array_equal(perm.cpu().numpy().view(np.uint32), ref["idx"]), kind
+            assert_hits_match(rr.hits_to_numpy(hits), ref["hits"], ref["rays"], w.tris, str(kind))
 
 
 def test_fused_call_msd_flag_checks(rr):
