@@ -13,8 +13,10 @@
 //    LDS word); for the fused call's dense sort, k_keys_hist computes the
 //    keys from the rays and counts them in the same pass instead;
 //  * k_seg_pass blocks (512 threads) are persistent.  A sort that has the
-//    device to itself takes tiles in a fixed order (block b: tiles b,
-//    b + G, ...), so no shared tile counter is contended; the batched layer,
+//    device to itself takes tiles in a fixed order (round r of G tiles:
+//    runs of 16 consecutive tiles dealt to the XCDs in turn, so that the
+//    seams between neighbouring tiles' digit runs meet in one L2), so no
+//    shared tile counter is contended; the batched layer,
 //    whose sorts may share the device with other kernels, by default takes
 //    them in order from an atomic counter, so that a tile is only ever held
 //    by a running block (each block takes its next ticket while it works on
@@ -53,6 +55,7 @@ namespace {
 constexpr int kSortThreads = 512;
 constexpr int kSortWaves = kSortThreads / kWave;
 constexpr uint32_t kGroup = 8;           // tiles per look-back group
+constexpr uint32_t kTileRun = 16;        // consecutive tiles of one XCD in the fixed tile order
 constexpr uint32_t kTileWindow = kGroup - 1;  // tile words read per look-back round
 constexpr uint32_t kGroupWindow = kGroup;     // group words read per look-back round
 constexpr uint32_t kFallbackSpins = 128;       // polls of an unpublished entry before computing it
@@ -536,13 +539,28 @@ __global__ __launch_bounds__(kSortThreads) void k_seg_pass(const K* __restrict__
       v[j] = ok ? ib[pos] : 0u;
     }
   };
-  // tiles in a fixed order, or in order from the counter (tile_counter)
+  // tiles in a fixed order, or in order from the counter (tile_counter).
+  // The fixed order is XCD-aware: workgroups go to the XCDs round-robin, so
+  // block b would take tile b and neighbouring tiles would sit on different
+  // XCDs.  Instead every round of gridDim.x tiles is cut into runs of
+  // kTileRun consecutive tiles, dealt to the XCDs in turn.  A digit's run
+  // from tile t ends where tile t + 1's run of that digit starts, so within
+  // a tile run the partial cache lines at those seams meet in one L2 before
+  // they are written back.  The runs are short, so the tiles in flight stay
+  // a narrow window and look-backs find their predecessors started.
+  // Blocks past the last whole span of kXcds runs keep tile = block.
   const bool counted = tile_counter != nullptr;
   if (counted) {
     if (tid == 0) sm.ticket = atomicAdd(tile_counter, 1u);
     __syncthreads();
   }
-  uint32_t tile = counted ? sm.ticket : blockIdx.x;
+  uint32_t tile = blockIdx.x;
+  if (counted) {
+    tile = sm.ticket;
+  } else if (blockIdx.x < gridDim.x / (kXcds * kTileRun) * (kXcds * kTileRun)) {
+    const uint32_t x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+    tile = j / kTileRun * (kXcds * kTileRun) + x * kTileRun + j % kTileRun;
+  }
   uint32_t s = 0;
   SortSeg sg{};
   if (tile < T) {
