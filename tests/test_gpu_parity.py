@@ -199,6 +199,23 @@ def test_sort_edge_distributions(rr, bits, case):
         assert np.array_equal(idx_np(idx), idx_in[perm]), (case, cfg)
 
 
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("n", [1_228_801, 2_621_443])
+def test_sort_tile_runs_per_xcd(rr, n, bits):
+    """Sizes where the fixed tile order deals runs of 16 tiles to the XCDs:
+    ~300 tiles (whole spans of 128 tiles, then blocks that keep their own
+    tile) and ~640 tiles (more tiles than resident blocks, a partial last
+    round); reversed input indices, 2^20 distinct keys."""
+    k = _random_keys(n, bits, n + bits, bits - 20)
+    idx_in = np.arange(n, dtype=np.uint32)[::-1].copy()
+    _, perm = O.sort_pairs(k)
+    kd = to_dev(k.view(np.int32 if bits == 32 else np.int64))
+    idx = to_dev(idx_in.view(np.int32))
+    rr.rr_sort(kd, idx)
+    assert np.array_equal(keys_np(kd, bits), k[perm])
+    assert np.array_equal(idx_np(idx), idx_in[perm])
+
+
 def test_sort_past_2_24_with_device_count(rr):
     """The 16-keys-per-thread configuration rr_sort takes from 2^24 keys on,
     with a device count below the capacity and 2^20 distinct 64-bit keys."""
