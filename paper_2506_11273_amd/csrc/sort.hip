@@ -1123,8 +1123,10 @@ __global__ __launch_bounds__(kLocThreads) void k_msd_local(K* __restrict__ keys,
 // row by row with wave64 ballots (the lowest lane of each group of equal
 // digits adds the group's size to the wave's counter with one LDS atomic),
 // scans the 256 counters across the wave and moves the keys through the
-// wave's own LDS; one wave's LDS operations take effect in order, so no
-// barrier is needed.  A bucket sits at [bstart, bstart + bcount) after the
+// wave's own LDS.  One wave's LDS operations take effect in order, so no
+// block barrier is needed; a wave barrier (no instruction) at each
+// exchange between lanes keeps the compiler from moving LDS accesses
+// across it.  A bucket sits at [bstart, bstart + bcount) after the
 // dl pass and the keys there are in input order, so the result is the
 // stable sort.  The gather of the fused call moves each ray to its slot.
 constexpr int kWaveThreads = 256;
@@ -1183,7 +1185,9 @@ __global__ __launch_bounds__(kWaveThreads) void k_msd_wave(K* __restrict__ keys,
     for (uint32_t d = 0; d < P; ++d) {
       if (d == dh || d == dl || ((dm >> d) & 1u) == 0) continue;
       moved = true;
+      __builtin_amdgcn_wave_barrier();  // the last pass's reads of lc, lk and li are done
       for (uint32_t i = lane; i < 256; i += kWave) lc[i] = 0;
+      __builtin_amdgcn_wave_barrier();
       uint32_t dg[kWaveKpt], rank[kWaveKpt], old[kWaveKpt];
 #pragma unroll
       for (int j = 0; j < kWaveKpt; ++j) {
@@ -1204,6 +1208,7 @@ __global__ __launch_bounds__(kWaveThreads) void k_msd_wave(K* __restrict__ keys,
       for (int j = 0; j < kWaveKpt; ++j)
         if ((uint32_t)j < rows)
           rank[j] = (rank[j] & 0xFFFFu) + (uint32_t)__shfl((int)old[j], (int)(rank[j] >> 16), kWave);
+      __builtin_amdgcn_wave_barrier();
       // exclusive offsets of the 256 digits: lane l owns digits 4l .. 4l + 3
       const uint32_t c0 = lc[4 * lane], c1 = lc[4 * lane + 1], c2 = lc[4 * lane + 2], c3 = lc[4 * lane + 3];
       uint32_t tot;
@@ -1212,6 +1217,7 @@ __global__ __launch_bounds__(kWaveThreads) void k_msd_wave(K* __restrict__ keys,
       lc[4 * lane + 1] = ex + c0;
       lc[4 * lane + 2] = ex + c0 + c1;
       lc[4 * lane + 3] = ex + c0 + c1 + c2;
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int j = 0; j < kWaveKpt; ++j) {
         if (lane + kWave * j < m) {
@@ -1220,6 +1226,7 @@ __global__ __launch_bounds__(kWaveThreads) void k_msd_wave(K* __restrict__ keys,
           li[at] = v[j];
         }
       }
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int j = 0; j < kWaveKpt; ++j) {
         const uint32_t p = lane + kWave * j;
