@@ -299,17 +299,16 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
         cswap(d1, c1, d3, c3);
         cswap(d1, c1, d2, c2);
         // push the farther hits, farthest first, so the next nearest pops
-        // first; while no lane can reach the scratch part (decided
-        // wave-uniformly) the pushes are plain LDS writes
+        // first.  While no lane can reach the scratch part (decided
+        // wave-uniformly) every lane writes three LDS slots without a
+        // branch: the m - 1 farther hits at sp.., the slots above the new
+        // top receive copies that are never read.
         const int32_t cs[3] = {c1, c2, c3};
         if (!__ballot(sp + 3 > kLdsStack)) {
-#pragma unroll
-          for (int k = 2; k >= 0; --k) {
-            if (k + 1 < m) {
-              lstack[sp * BLOCK] = cs[k];
-              ++sp;
-            }
-          }
+          lstack[sp * BLOCK] = m == 4 ? c3 : (m == 3 ? c2 : c1);
+          lstack[(sp + 1) * BLOCK] = m == 4 ? c2 : c1;
+          lstack[(sp + 2) * BLOCK] = c1;
+          sp += m - 1;
         } else {
 #pragma unroll
           for (int k = 2; k >= 0; --k) {
