@@ -357,17 +357,19 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
         const float py = R.dz * e2x - R.dx * e2z;
         const float pz = R.dx * e2y - R.dy * e2x;
         const float det = (e1x * px + e1y * py) + e1z * pz;
-        if (det == 0.0f) continue;
+        // every quantity is computed and the tests are combined into one
+        // predicate: the lanes of a wave test different triangles, so early
+        // exits would seldom skip work and only add branches (det = 0 gives
+        // an infinite or NaN u, which the predicate rejects as well)
         const float inv = 1.0f / det;
         const float u = ((sx * px + sy * py) + sz * pz) * inv;
-        if (!(u >= 0.0f && u <= 1.0f)) continue;
         const float qx = sy * e1z - sz * e1y;
         const float qy = sz * e1x - sx * e1z;
         const float qz = sx * e1y - sy * e1x;
         const float v = ((R.dx * qx + R.dy * qy) + R.dz * qz) * inv;
-        if (!(v >= 0.0f && u + v <= 1.0f)) continue;
         const float t = ((e2x * qx + e2y * qy) + e2z * qz) * inv;
-        if (t > R.tmin && (t < tbest || (t == tbest && prim < bprim))) {
+        const bool inside = det != 0.0f && u >= 0.0f && u <= 1.0f && v >= 0.0f && u + v <= 1.0f;
+        if (inside && t > R.tmin && (t < tbest || (t == tbest && prim < bprim))) {
           tbest = t;
           bprim = prim;
           bu = u;
