@@ -288,43 +288,44 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
         h3 = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, R, tbest, &t3) && cc.w != kEmptyChild;
       }
       const int m = (int)h0 + (int)h1 + (int)h2 + (int)h3;
-      if (m > 0) {
-        const float inf = __int_as_float(0x7f800000);
-        float d0 = h0 ? t0 : inf, d1 = h1 ? t1 : inf, d2 = h2 ? t2 : inf, d3 = h3 ? t3 : inf;
-        int32_t c0 = cc.x, c1 = cc.y, c2 = cc.z, c3 = cc.w;
-        // nearest first; misses (inf) sort last
-        cswap(d0, c0, d1, c1);
-        cswap(d2, c2, d3, c3);
-        cswap(d0, c0, d2, c2);
-        cswap(d1, c1, d3, c3);
-        cswap(d1, c1, d2, c2);
-        // push the farther hits, farthest first, so the next nearest pops
-        // first.  While no lane can reach the scratch part (decided
-        // wave-uniformly) every lane writes three LDS slots without a
-        // branch: the m - 1 farther hits at sp.., the slots above the new
-        // top receive copies that are never read.
+      const float inf = __int_as_float(0x7f800000);
+      float d0 = h0 ? t0 : inf, d1 = h1 ? t1 : inf, d2 = h2 ? t2 : inf, d3 = h3 ? t3 : inf;
+      int32_t c0 = cc.x, c1 = cc.y, c2 = cc.z, c3 = cc.w;
+      // nearest first; misses (inf) sort last
+      cswap(d0, c0, d1, c1);
+      cswap(d2, c2, d3, c3);
+      cswap(d0, c0, d2, c2);
+      cswap(d1, c1, d3, c3);
+      cswap(d1, c1, d2, c2);
+      if (!__ballot(sp + 3 > kLdsStack)) {
+        // no lane can reach the scratch part (decided wave-uniformly):
+        // every lane reads the entry below its top and writes three slots
+        // from its top, without a branch.  With hits the m - 1 farther
+        // ones go to sp.. (farthest deepest; the slots above the new top
+        // receive copies that are never read) and the nearest is next;
+        // without, the entry below the top is popped.
+        const int32_t below = lstack[(sp > 0 ? sp - 1 : 0) * BLOCK];
+        lstack[sp * BLOCK] = m == 4 ? c3 : (m == 3 ? c2 : c1);
+        lstack[(sp + 1) * BLOCK] = m == 4 ? c2 : c1;
+        lstack[(sp + 2) * BLOCK] = c1;
+        node = m > 0 ? c0 : (sp > 0 ? below : kEmptyChild);
+        sp = m > 0 ? sp + m - 1 : (sp > 0 ? sp - 1 : 0);
+      } else if (m > 0) {
         const int32_t cs[3] = {c1, c2, c3};
-        if (!__ballot(sp + 3 > kLdsStack)) {
-          lstack[sp * BLOCK] = m == 4 ? c3 : (m == 3 ? c2 : c1);
-          lstack[(sp + 1) * BLOCK] = m == 4 ? c2 : c1;
-          lstack[(sp + 2) * BLOCK] = c1;
-          sp += m - 1;
-        } else {
 #pragma unroll
-          for (int k = 2; k >= 0; --k) {
-            if (k + 1 < m) {
-              if (sp < kLdsStack) lstack[sp * BLOCK] = cs[k];
-              else spill[sp - kLdsStack] = cs[k];
-              if (STATS && sp >= kLdsStack) ++st_spill;
-              ++sp;
-            }
+        for (int k = 2; k >= 0; --k) {
+          if (k + 1 < m) {
+            if (sp < kLdsStack) lstack[sp * BLOCK] = cs[k];
+            else spill[sp - kLdsStack] = cs[k];
+            if (STATS && sp >= kLdsStack) ++st_spill;
+            ++sp;
           }
         }
-        if (STATS && (unsigned long long)sp > st_depth) st_depth = (unsigned long long)sp;
         node = c0;
       } else {
         node = pop_or_none();
       }
+      if (STATS && (unsigned long long)sp > st_depth) st_depth = (unsigned long long)sp;
       if (node < 0 && leaf == 0) {
         leaf = node;
         node = pop_or_none();
