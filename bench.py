@@ -722,13 +722,17 @@ def bounce3(torch, rr, W, scene, dev, stream, steps):
     return out
 
 
-def sort_sizes(torch, rr, dev, stream, reps=7):
+def sort_sizes(torch, rr, dev, stream, reps=15):
     """rr_sort of seeded uniform random keys with indices 0..n-1 at the two
     wavefront sizes and at 64M pairs (beyond the 256 MB last-level cache),
     32- and 64-bit keys, against the HBM roofline of the 8-bit schedule; for
     64-bit keys also rr_sort_msd of the same keys (entries ending in _msd).
-    Each result is checked (keys non-decreasing as unsigned words, equal keys
-    in ascending index order, indices a permutation)."""
+    Every sort starts from the same input, restored by a copy: the time is
+    the median of copy and sort issued back to back, minus the median of the
+    copy alone (a single call bracketed by events would also time the host
+    issuing its kernels, longer than a sort of 2M pairs).  Each result is
+    checked (keys non-decreasing as unsigned words, equal keys in ascending
+    index order, indices a permutation)."""
     out = {}
     for n in (2073600, 8294400, 67108864):
         for bits in (32, 64):
@@ -741,19 +745,19 @@ def sort_sizes(torch, rr, dev, stream, reps=7):
             k = torch.empty_like(k0)
             i = torch.empty_like(i0)
             ws = rr.workspace(rr.sort_workspace_size(n, bits), dev)
+            def restore():
+                k.copy_(k0)
+                i.copy_(i0)
+
             for msd in ((False, True) if bits == 64 else (False,)):
-                times = []
-                for _ in range(reps):
-                    k.copy_(k0)
-                    i.copy_(i0)
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e1 = torch.cuda.Event(enable_timing=True)
-                    e0.record(stream)
+                def run():
+                    restore()
                     rr.rr_sort(k, i, key_bits=bits, ws=ws, msd=msd)
-                    e1.record(stream)
-                    torch.cuda.synchronize()
-                    times.append(e0.elapsed_time(e1))
-                ms = float(np.median(times[1:]))
+
+                run()
+                ms = median_ms(torch, stream, run, reps) - median_ms(torch, stream, restore, reps)
+                run()
+                torch.cuda.synchronize()
                 flip = k ^ torch.tensor(lo, dtype=dt, device=dev)  # unsigned order as signed order
                 ok = bool((flip[1:] >= flip[:-1]).all())
                 ties = flip[1:] == flip[:-1]
