@@ -26,11 +26,12 @@
 // (e2.z, prim id bits, -, -), with e1 = v1 - v0 and e2 = v2 - v0.
 //
 // Execution: persistent wavefronts.  Each XCD owns a contiguous share of
-// the ray slots (in key order when the rays were reordered); its waves take
-// 64-slot packets of that share in turn, and a wave refills its idle lanes
-// from its packets whenever at least `refill` lanes are idle, so lanes whose
-// rays finish early do not idle until the wave's longest ray ends, and the
-// rays in flight on an XCD stay a window of neighbouring slots.
+// the ray slots (in key order when the rays were reordered); its blocks take
+// packets of that share in turn (16 to 64 slots, chosen per launch), and a
+// wave refills its idle lanes from its block's packets whenever at least
+// `refill` lanes are idle, so lanes whose rays finish early do not idle until
+// the wave's longest ray ends, the waves of a block run out of rays together,
+// and the rays in flight on an XCD stay a window of neighbouring slots.
 // A wave alternates between an inner-node loop and a leaf loop (while-while
 // traversal, a found leaf postponed while the lane goes on with inner nodes).
 // Neither loop runs until its last lane is done: the inner loop ends once at
@@ -53,8 +54,8 @@ constexpr float kFarSlack = 0x1p-16f;
 constexpr float kTinyDir = 1e-20f;
 constexpr int kLdsStack = 16;
 constexpr int kSpillStack = kTraceStack4 - kLdsStack;
-// A wave takes packets of 2^pshift consecutive ray slots in turn (16 to 64
-// slots, chosen per launch; see launch4q).
+// Packets are 2^pshift consecutive ray slots (16 to 64, chosen per launch;
+// see launch4q).
 constexpr int kLoopExit = 8;      // lanes left in a loop when the wave moves on
 
 __device__ __forceinline__ uint32_t read_count(const uint32_t* count_dev, uint32_t n_max) {
@@ -168,20 +169,27 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
   const uint32_t xb0 = x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q;  // XCD's first block
   const uint32_t xbn = x < rem ? q + 1 : q;                                    // and its block count
   const uint32_t wpb = BLOCK / kWave;
-  // The XCD's share of the ray slots is [xs, xe); its W waves take
-  // packets of 2^pshift slots of it in turn (wave wx: packets wx, wx + W,
-  // wx + 2W, ...), so the waves of an XCD move through the share together
-  // and the rays in flight on it at any time are a window of consecutive
-  // slots.
-  const uint32_t W = xbn * wpb, wx = j * wpb + threadIdx.x / kWave;
+  // The XCD's share of the ray slots is [xs, xe), cut into packets of
+  // 2^pshift slots.  With W waves on the XCD, wpb per block, the block whose
+  // first wave is w0 holds packets k W + w0 .. k W + w0 + wpb - 1 for k = 0,
+  // 1, ... (as if wave w took packets w, w + W, w + 2W, ...), so the blocks of
+  // an XCD move through the share together and the rays in flight on it at
+  // any time are a window of consecutive slots.  The block's waves take its
+  // rays in that order from a counter in LDS, as many at a time as they have
+  // idle lanes: a wave whose rays finish early takes more, and the block's
+  // waves run out of rays together instead of each after a fixed share.
+  const uint32_t W = xbn * wpb, w0 = j * wpb;
   const uint32_t xs = (uint32_t)(((uint64_t)xb0 * wpb * n) / waves);
   const uint32_t xe = (uint32_t)(((uint64_t)(xb0 + xbn) * wpb * n) / waves);
-  // slot of this wave's v-th ray (monotonic in v)
+  // slot of the block's v-th ray (monotonic in v)
   const uint32_t pk = 1u << pshift;
   auto slot_of = [&](uint32_t v) -> uint64_t {
-    return (uint64_t)xs + ((uint64_t)(v >> pshift) * W + wx) * pk + (v & (pk - 1));
+    const uint32_t q = v >> pshift;
+    return (uint64_t)xs + ((uint64_t)(q / wpb) * W + w0 + q % wpb) * pk + (v & (pk - 1));
   };
-  uint32_t next = 0;  // rays this wave has taken
+  __shared__ uint32_t s_taken;  // rays the block's waves have taken
+  if (threadIdx.x == 0) s_taken = 0;
+  __syncthreads();
   int32_t* lstack = s_stack + threadIdx.x;
 
   Ray R{};
@@ -198,11 +206,17 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
     // ---- refill idle lanes from the wave's packets (wave-uniform decision)
     const uint64_t idle = __ballot(slot < 0);
     const uint32_t n_idle = (uint32_t)__popcll(idle);
-    const bool more = slot_of(next) < xe;
+    const bool more = slot_of(__hip_atomic_load(&s_taken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) < xe;
     if (n_idle == kWave && !more) break;
     if (more && (n_idle >= refill || n_idle == kWave)) {
+      // one lane takes n_idle rays for the wave (another wave may have
+      // taken the last ones since the check: lanes past the share stay idle)
+      const int first = __builtin_ctzll(__ballot(1));
+      uint32_t base = 0;
+      if ((int)lane == first) base = atomicAdd(&s_taken, n_idle);
+      base = __shfl(base, first, kWave);
       if (slot < 0) {
-        const uint64_t s64 = slot_of(next + lanes_below(idle));
+        const uint64_t s64 = slot_of(base + lanes_below(idle));
         if (s64 < xe) {
           const uint32_t s = (uint32_t)s64;
           slot = (int32_t)s;
@@ -232,7 +246,6 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
           if (STATS) ++st_rays;
         }
       }
-      next += n_idle;
     }
     // counts one wave iteration per wave (by the lowest active lane)
     auto wave_tick = [&]() {
@@ -666,15 +679,16 @@ rr_status launch4q(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx
   const uint64_t waves_needed = (uint64_t)(n_max + kWave - 1) / kWave;
   const uint64_t blocks_needed = (waves_needed + BLOCK / kWave - 1) / (BLOCK / kWave);
   const uint32_t blocks = (uint32_t)std::min<uint64_t>(blocks_needed, resident_blocks<BLOCK, STATS, QNODE, ANY>());
-  // Packet size.  A wave's work is the sum over its packets, and the launch
-  // ends with its slowest wave.  In key order neighbouring rays cost alike,
-  // so a wave needs enough packets for their costs to even out, while
-  // larger packets keep a wave's rays together.  The choice is about 16
-  // packets per wave: the power of two nearest in ratio, within 16 to 64
+  // Packet size.  A block's work is the sum over its packets, and the
+  // launch ends with its slowest block.  In key order neighbouring rays cost
+  // alike, so a block needs enough packets for their costs to even out,
+  // while larger packets keep a wave's rays together.  The choice is about
+  // 16 packets per wave: the power of two nearest in ratio, within 16 to 64
   // slots.  Measured on city wavefronts: at ~250 rays per wave (1080p),
-  // 16-slot packets trace Two Point order 7-9% faster than 64-slot ones,
+  // 16-slot packets trace Two Point order 7-11% faster than 64-slot ones,
   // with pixel and shuffled order within 1-2%; at ~1,000 rays per wave
-  // (2160p), 64 slots beat 16, 8 and 4 by 1-11%.
+  // (2160p), 64 slots beat 16, 8 and 4 by 1-11%.  About 8 packets per wave
+  // was within 2% (faster in key and shuffled order, slower in pixel order).
   const uint64_t waves = (uint64_t)blocks * (BLOCK / kWave);
   const uint64_t per_wave = ((uint64_t)n_max + waves - 1) / waves;
   uint32_t pshift = 4;
