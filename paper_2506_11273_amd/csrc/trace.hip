@@ -203,7 +203,7 @@ __global__ __launch_bounds__(BLOCK) void k_trace4(const float4* __restrict__ nod
   unsigned long long st_depth = 0, st_spill = 0;
 
   while (true) {
-    // ---- refill idle lanes from the wave's packets (wave-uniform decision)
+    // ---- refill idle lanes from the block's packets (wave-uniform decision)
     const uint64_t idle = __ballot(slot < 0);
     const uint32_t n_idle = (uint32_t)__popcll(idle);
     const bool more = slot_of(__hip_atomic_load(&s_taken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) < xe;
