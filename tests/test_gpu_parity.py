@@ -318,6 +318,33 @@ def test_trace_ragged_counts_and_refill(rr, soup65k):
     assert_hits_match(rr.hits_to_numpy(full), ref, rays, w.tris, "full")
 
 
+def test_persistent_trace_device_counts(rr, soup65k):
+    """The one-lane persistent trace (rr_trace with a refill threshold) under a
+    device-side ray count below the capacity.  The count sets where the XCD
+    shares end, and the waves of a block take rays from the block's packets
+    through a shared counter until the share is used up.  Counts of 0 and 1,
+    around packets and blocks, and just below the capacity, each at three
+    refill thresholds: the oracle's hits for the counted rays, and the slots
+    past the count left untouched."""
+    w = soup65k
+    N = 30011
+    rays = np.ascontiguousarray(w.rays[:N])
+    ref = O.brute_force(w.tris, rays)
+    dr = to_dev(rays)
+    out = torch.empty((N, 4), dtype=torch.float32, device=DEV)
+    with rr.Scene(w.tris, builder=1) as sc:
+        for count in (0, 1, 255, 257, 6161, 16385, N - 1, N):
+            cnt = torch.tensor([count], dtype=torch.int32, device=DEV)
+            for refill in (1, 16, 64):
+                out.fill_(-3.0)
+                rr.rr_trace(sc, dr, count=cnt, hits=out, refill=refill)
+                torch.cuda.synchronize()
+                assert bool((out[count:] == -3.0).all()), (count, refill)
+                if count:
+                    assert_hits_match(rr.hits_to_numpy(out[:count]), ref[:count], rays[:count], w.tris,
+                                      f"count={count} refill={refill}")
+
+
 def test_four_lane_trace_equals_the_persistent_kernel(rr):
     """rr_trace traces small launches with four lanes per ray (up to what one
     resident wave of its blocks holds, about 98K rays) and larger ones with
