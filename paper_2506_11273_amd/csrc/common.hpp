@@ -18,7 +18,7 @@ constexpr int kMaxTreeDepth = 32;      // binary BVH leaf depth cap (the builder
 // never deeper than the binary node it was collapsed from.
 constexpr int kTraceStack4 = 3 * kMaxTreeDepth;
 constexpr int32_t kEmptyChild = 0x7FFFFFFF;  // unused child slot of a 4-wide node
-constexpr uint32_t kDefaultRefill = 16;      // idle lanes that trigger a wave refill
+constexpr uint32_t kDefaultRefill = 16;      // idle lanes that trigger a wave refill (below 512 rays per wave)
 constexpr uint32_t kStatusCountMask = 0x3FFFFFFFu;
 constexpr uint32_t kStatusAggregate = 1u << 30;
 constexpr uint32_t kStatusPrefix = 2u << 30;

@@ -693,6 +693,12 @@ rr_status launch4q(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx
   const uint64_t per_wave = ((uint64_t)n_max + waves - 1) / waves;
   uint32_t pshift = 4;
   while (pshift < 6 && per_wave * 5 >= (uint64_t)113 << pshift) ++pshift;  // per_wave / 2^pshift >= 16 sqrt 2
+  // Refill threshold when the caller leaves it to the launch (0): 16, and 24
+  // from 512 rays per wave on.  Measured against 16 on city wavefronts: at
+  // ~1,000 rays per wave (2160p) 24 traced Two Point order ~3% faster and
+  // pixel order ~1%, shuffled rays 0.5% slower; at ~250 rays per wave (1080p)
+  // it was within 1%.
+  if (refill == 0) refill = per_wave >= 512 ? 24u : kDefaultRefill;
   hipLaunchKernelGGL((k_trace4<BLOCK, STATS, QNODE, ANY>), dim3(blocks), dim3(BLOCK), 0, st, s.nodes, s.tris, s.root,
                      reinterpret_cast<const float4*>(rays), idx, count_dev, (uint32_t)n_max,
                      reinterpret_cast<float4*>(hits), refill, pshift, stats);
@@ -705,8 +711,7 @@ rr_status launch4(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx,
                   const uint32_t* count_dev, rr_hit* hits, uint32_t refill, TraceStats* stats, hipStream_t st,
                   uint32_t block = kTraceBlock) {
   if (n_max <= 0) return RR_OK;
-  if (refill < 1) refill = 1;
-  if (refill > (uint32_t)kWave) refill = kWave;
+  if (refill > (uint32_t)kWave) refill = kWave;  // 0: chosen per launch (launch4q)
   // the other block sizes exist for the closest-hit trace on quantised nodes
   if (!STATS && !ANY && s.quantised && block == 128)
     return launch4q<128, false, true, false>(s, rays, idx, n_max, count_dev, hits, refill, stats, st);
@@ -724,7 +729,7 @@ rr_status launch_trace(const DeviceScene& s, const rr_ray* rays, const uint32_t*
   if (n_max <= 0) return RR_OK;
   if (s.quantised && n_max <= quad_capacity())
     return launch_quad<false>(s, rays, idx, n_max, count_dev, hits, st);
-  return launch4<false>(s, rays, idx, n_max, count_dev, hits, kDefaultRefill, nullptr, st);
+  return launch4<false>(s, rays, idx, n_max, count_dev, hits, 0u, nullptr, st);
 }
 
 rr_status launch_trace_refill(const DeviceScene& s, const rr_ray* rays, const uint32_t* idx, int64_t n_max,
@@ -738,7 +743,7 @@ rr_status launch_trace_any(const DeviceScene& s, const rr_ray* rays, const uint3
   if (n_max <= 0) return RR_OK;
   if (s.quantised && n_max <= quad_capacity())
     return launch_quad<true>(s, rays, idx, n_max, count_dev, hits, st);
-  return launch4<false, true>(s, rays, idx, n_max, count_dev, hits, kDefaultRefill, nullptr, st);
+  return launch4<false, true>(s, rays, idx, n_max, count_dev, hits, 0u, nullptr, st);
 }
 
 void trace_warm() {
@@ -755,7 +760,7 @@ void trace_warm() {
 
 rr_status launch_trace_stats(const DeviceScene& s, const rr_ray* rays, int64_t n_max, rr_hit* hits,
                              uint64_t* stats_dev, hipStream_t st) {
-  return launch4<true>(s, rays, nullptr, n_max, nullptr, hits, kDefaultRefill,
+  return launch4<true>(s, rays, nullptr, n_max, nullptr, hits, 0u,
                        reinterpret_cast<TraceStats*>(stats_dev), st);
 }
 
