@@ -76,6 +76,23 @@ def test_headline_keys_and_fused_call(rr, city, kind, bits):
     assert h.tobytes() == plain[want_perm].tobytes()
 
 
+def test_large_launch_refill(rr, city):
+    """A launch of more than 512 rays per resident wave (the headline rays
+    three times over, 6.2M rays), where rr_trace takes its larger refill
+    threshold: the same hits bit for bit as rr_trace_ex with refill 8, and
+    each copy the same as the trace of the wavefront alone (whose hits the
+    headline test checks against the oracle)."""
+    w, scene, _ = city
+    n = w.rays.shape[0]
+    rays = to_dev(np.concatenate([w.rays] * 3))
+    auto = rr.rr_trace(scene, rays)
+    fixed = rr.rr_trace(scene, rays, refill=8)
+    assert torch.equal(auto.view(torch.int32), fixed.view(torch.int32))
+    one = rr.rr_trace(scene, rays[:n])
+    for c in range(3):
+        assert torch.equal(auto[c * n:(c + 1) * n].view(torch.int32), one.view(torch.int32)), c
+
+
 def test_bounce3_compacted(rr, city):
     w, scene, bvh = city
     w3 = W.bounce3_2160p()
